@@ -1,0 +1,159 @@
+/* dghabc.h -- C ABI of the MI355X time stepper for nodal DG with high-order
+ * absorbing boundary conditions (HABCs) and corner/edge compatibility.
+ *
+ * Method: A. Modave, A. Atle, J. Chan, T. Warburton, "A GPU-accelerated
+ * nodal discontinuous Galerkin method with high-order absorbing boundary
+ * conditions and corner/edge compatibility", arXiv:1610.05023.
+ *
+ * Every function returns dgh_status (0 = DGH_OK).  Nothing aborts, throws or
+ * exits; on failure dgh_last_error() holds the reason.  One context per host
+ * thread; contexts share no state.
+ *
+ * Call order: dgh_create -> dgh_upload_mesh -> dgh_set_order -> dgh_set_habc
+ * -> dgh_set_material -> dgh_workspace_size -> dgh_bind_workspace ->
+ * (dgh_set_state | dgh_set_source)* -> (dgh_step | dgh_read_fields |
+ * dgh_energy)* -> dgh_destroy.  Calls out of order return DGH_ESTATE.
+ * Calls before dgh_bind_workspace touch no GPU.
+ *
+ * Memory: all host pointers are caller-owned and only read/written during the
+ * call.  Device memory is a single caller-owned workspace (e.g. a PyTorch
+ * uint8 tensor) that the library never allocates or frees; every device
+ * array of the method lives inside it.
+ *
+ * Canonical host layouts (row-major, FP64, leading shot index omitted when
+ * n_shots = 1):
+ *   q3, res3      [K][4][Np]          fields (p, u, v, w)
+ *   q2, res2      [Ktri][P][3][Np2]   (p_i, two tangential velocity
+ *                                      components in ascending axis order)
+ *   qb3, q0_3     [Ktri][Np2]         incoming characteristic, r+ + r-
+ *   q1, res1      [Klin][P*P][2][Np1] (p_ij, velocity along +axis); set
+ *                                      index i*P + j, i on the earlier face
+ *   qb2, q0_2     [Klin][2][P][Np1]   side 0 = earlier face (x-,x+,y-,...)
+ *   qb1           [Kpnt][3][P*P]      slot a = the line along axis a
+ * Node orders: tetrahedron lattice (i, j, k), i + j + k <= N, k slowest,
+ * i fastest, Warp & Blend positions; triangle = tet nodes with k = 0;
+ * line = GLL points.  Orderings of triangles, lines and corners are
+ * documented in paper_1610_05023_amd/csrc/mesh.hpp.
+ */
+#ifndef DGHABC_H
+#define DGHABC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dgh_ctx dgh_ctx;
+
+typedef enum {
+  DGH_OK = 0,
+  DGH_EINVAL = -1,     /* bad argument, size or range */
+  DGH_ESTATE = -2,     /* call out of order */
+  DGH_EHIP = -3,       /* a HIP runtime call failed */
+  DGH_ENOMEM = -4,     /* workspace too small */
+  DGH_ENONFINITE = -5, /* non-finite value found by dgh_check */
+  DGH_EUNSTABLE = -6   /* energy growth found by dgh_check */
+} dgh_status;
+
+typedef enum { DGH_FP64 = 0 } dgh_precision;
+
+/* Boundary condition of a face of the cuboid (faces x-, x+, y-, y+, z-, z+).
+ * HABC: Pade HABC of order P (Section 2), with edge/corner compatibility where
+ * two/three HABC faces meet; ABC: the basic ABC, incoming characteristic 0
+ * (Section 3.2); DIRICHLET: p = 0 (Sections 2.4, 3.2); PERIODIC: both faces
+ * of that axis are identified (used for plane-wave checks). */
+typedef enum { DGH_BC_HABC = 0, DGH_BC_ABC = 1, DGH_BC_DIRICHLET = 2, DGH_BC_PERIODIC = 3 } dgh_bc;
+
+/* Indices of the state arrays passed to dgh_set_state / dgh_read_fields. */
+enum {
+  DGH_Q3 = 0, DGH_RES3, DGH_Q2, DGH_RES2, DGH_QB3, DGH_Q03,
+  DGH_Q1, DGH_RES1, DGH_QB2, DGH_Q02, DGH_QB1, DGH_NARRAYS
+};
+
+/* Counts reported by dgh_counts (indices into the int array). */
+enum {
+  DGH_C_K = 0, DGH_C_KTRI, DGH_C_KLIN, DGH_C_KPNT, DGH_C_NP, DGH_C_NP2, DGH_C_NP1,
+  DGH_C_P, DGH_C_N, DGH_C_NSHOTS, DGH_NCOUNTS
+};
+
+/* Creates a context for HIP device `device`.  precision: DGH_FP64.
+ * n_shots: number of independent right-hand sides stepped together (1). */
+dgh_status dgh_create(dgh_ctx** out, int device, int precision, int n_shots);
+
+/* Tetrahedral mesh of the cuboid box = {lo[3], hi[3]} (Section 3.2: volume
+ * mesh of K tetrahedra).  VX: Nv x 3 coordinates; EToV: K x 4 vertex ids,
+ * each tetrahedron positively oriented.  periodic[3] (may be NULL): identify
+ * the two faces of that axis.  The mesh must be conforming. */
+dgh_status dgh_upload_mesh(dgh_ctx* ctx, int Nv, const double* VX, int K, const int* EToV,
+                           const double* box /* lo[3], hi[3] */, const int* periodic);
+
+/* Polynomial degree N of the nodal basis, 1 <= N <= 6 (Section 3.2). */
+dgh_status dgh_set_order(dgh_ctx* ctx, int N);
+
+/* HABC order P (0 <= P <= 12) and optional coefficients gamma[P] (NULL: the
+ * Pade values tan^2(n pi/(2P+1)), Section 2.1); face_bc[6] per face
+ * (NULL: HABC everywhere).  Builds the surface, line and corner meshes and
+ * the edge/corner maps (Section 3.1). */
+dgh_status dgh_set_habc(dgh_ctx* ctx, int P, const double* gamma, const int* face_bc);
+
+/* Cellwise density rho[K] > 0 and wave speed c[K] > 0 (Section 2, the
+ * pressure-velocity system; Section 3.2, cellwise constant materials). */
+dgh_status dgh_set_material(dgh_ctx* ctx, const double* rho, const double* c);
+
+/* Number of elements per level and sizes; out[DGH_NCOUNTS]. */
+dgh_status dgh_counts(const dgh_ctx* ctx, int* out);
+
+/* Physical coordinates of the tetrahedron nodes, K x Np x 3 (host). */
+dgh_status dgh_node_coords(const dgh_ctx* ctx, double* out);
+
+/* Bytes of device workspace the context needs. */
+dgh_status dgh_workspace_size(dgh_ctx* ctx, size_t* bytes);
+
+/* Binds the caller-owned device workspace (>= dgh_workspace_size bytes,
+ * 256-byte aligned) and uploads operators, geometry, connectivity and HABC
+ * maps; zeroes the state.  `stream` is a hipStream_t (NULL = default). */
+dgh_status dgh_bind_workspace(dgh_ctx* ctx, void* device_ptr, size_t bytes, void* stream);
+
+/* Sets the state of one shot from host arrays in the canonical layouts;
+ * arrays[DGH_NARRAYS], a NULL entry means zeros.  Synchronises the stream. */
+dgh_status dgh_set_state(dgh_ctx* ctx, int shot, const double* const* arrays);
+
+/* Copies the state of one shot to host arrays (NULL entries are skipped).
+ * Synchronises the stream. */
+dgh_status dgh_read_fields(dgh_ctx* ctx, int shot, double* const* arrays);
+
+/* Point source delta(x - xs) S(t) in the pressure equation with
+ * S(t) = amp (t - t0) exp(-pi^2 f0^2 (t - t0)^2), the integral of a Ricker
+ * wavelet of peak frequency f0 (Section 4.1).  The source is projected on
+ * the element that contains xs (the most interior one on ties).  amp = 0
+ * removes the source of that shot. */
+dgh_status dgh_set_source(dgh_ctx* ctx, int shot, const double* xs, double f0, double t0,
+                          double amp);
+
+/* Advances all shots by n_steps steps of the five-stage low-storage RK
+ * scheme (Section 3.2) with step dt, starting at time t_start; each stage
+ * runs the volume, face, edge and corner levels in the order of Algorithm 1.
+ * Asynchronous on the bound stream. */
+dgh_status dgh_step(dgh_ctx* ctx, int n_steps, double dt, double t_start);
+
+/* FP64 energy sum_k J_k/2 (p^T M p/(rho c^2) + rho u^T M u) of the 3D fields
+ * of one shot (the energy weights of Section 4.1).  Synchronises. */
+dgh_status dgh_energy(dgh_ctx* ctx, int shot, double* e);
+
+/* Per-kernel timing with HIP events on the bound stream: enable = 1 starts
+ * recording around every 3D-level launch, 0 stops.  dgh_kernel_time returns
+ * the accumulated milliseconds and launch count of level `level` (3, 2, 1,
+ * 0) since the last enable. Synchronises. */
+dgh_status dgh_kernel_timing(dgh_ctx* ctx, int enable);
+dgh_status dgh_kernel_time(dgh_ctx* ctx, int level, double* total_ms, long long* launches);
+
+/* Reason of the last failure (never NULL). */
+const char* dgh_last_error(const dgh_ctx* ctx);
+
+void dgh_destroy(dgh_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGHABC_H */

@@ -1,0 +1,215 @@
+"""Thin ctypes binding of libdghabc (include/dghabc.h).
+
+Argument marshalling only: every step of the time stepper runs in the
+library's HIP kernels.  PyTorch provides the device workspace (a uint8
+tensor) and the stream.  The binding raises if the library is missing: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdghabc.so")
+
+DGH_OK = 0
+STATUS = {0: "DGH_OK", -1: "DGH_EINVAL", -2: "DGH_ESTATE", -3: "DGH_EHIP", -4: "DGH_ENOMEM",
+          -5: "DGH_ENONFINITE", -6: "DGH_EUNSTABLE"}
+BC = {"habc": 0, "abc": 1, "dirichlet": 2, "periodic": 3}
+ARRAYS = ["q3", "res3", "q2", "res2", "qb3", "q0_3", "q1", "res1", "qb2", "q0_2", "qb1"]
+COUNTS = ["K", "Ktri", "Klin", "Kpnt", "Np", "Np2", "Np1", "P", "N", "n_shots"]
+
+# exported names and their C signatures
+_SIGS = {
+    "dgh_create": [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int],
+    "dgh_upload_mesh": [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                        C.c_void_p],
+    "dgh_set_order": [C.c_void_p, C.c_int],
+    "dgh_set_habc": [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p],
+    "dgh_set_material": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "dgh_counts": [C.c_void_p, C.c_void_p],
+    "dgh_node_coords": [C.c_void_p, C.c_void_p],
+    "dgh_workspace_size": [C.c_void_p, C.POINTER(C.c_size_t)],
+    "dgh_bind_workspace": [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p],
+    "dgh_set_state": [C.c_void_p, C.c_int, C.c_void_p],
+    "dgh_read_fields": [C.c_void_p, C.c_int, C.c_void_p],
+    "dgh_set_source": [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_double, C.c_double],
+    "dgh_step": [C.c_void_p, C.c_int, C.c_double, C.c_double],
+    "dgh_energy": [C.c_void_p, C.c_int, C.POINTER(C.c_double)],
+    "dgh_kernel_timing": [C.c_void_p, C.c_int],
+    "dgh_kernel_time": [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
+    "dgh_last_error": [C.c_void_p],
+    "dgh_destroy": [C.c_void_p],
+}
+
+_lib = None
+
+
+def load():
+    """Loads the built library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        # torch first: its bundled HIP runtime has the same soname as the one
+        # the library links, so both then share a single runtime instance
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        lib = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = C.c_char_p if name == "dgh_last_error" else (
+                None if name == "dgh_destroy" else C.c_int)
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+class DghError(RuntimeError):
+    pass
+
+
+class Solver:
+    """One context of the library: mesh, order N, HABC order P, materials,
+    a torch-owned device workspace, and the stepping calls."""
+
+    def __init__(self, VX, EToV, N, P, rho, c, face_bc=None, periodic=None, box=None,
+                 gamma=None, device=0, precision=0, n_shots=1):
+        self.lib = load()
+        h = C.c_void_p()
+        st = self.lib.dgh_create(C.byref(h), device, precision, n_shots)
+        if st != DGH_OK:
+            raise DghError(f"dgh_create failed: {STATUS.get(st, st)}")
+        self.h = h
+        self.device = device
+        VX = np.ascontiguousarray(VX, dtype=np.float64)
+        EToV = np.ascontiguousarray(EToV, dtype=np.int32)
+        if box is None:
+            box = np.concatenate([VX.min(axis=0), VX.max(axis=0)])
+        box = np.ascontiguousarray(box, dtype=np.float64).ravel()
+        per = None if periodic is None else np.ascontiguousarray(
+            [1 if p else 0 for p in periodic], dtype=np.int32)
+        self._call("dgh_upload_mesh", VX.shape[0], _ptr(VX), EToV.shape[0], _ptr(EToV),
+                   _ptr(box), _ptr(per))
+        self._call("dgh_set_order", N)
+        fb = None
+        if face_bc is not None:
+            fb = np.ascontiguousarray([BC[b] if isinstance(b, str) else int(b) for b in face_bc],
+                                      dtype=np.int32)
+        g = None if gamma is None else np.ascontiguousarray(gamma, dtype=np.float64)
+        self._call("dgh_set_habc", P, _ptr(g), _ptr(fb))
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        self._call("dgh_set_material", _ptr(rho), _ptr(c))
+        cnt = np.zeros(len(COUNTS), dtype=np.int32)
+        self._call("dgh_counts", _ptr(cnt))
+        self.counts = dict(zip(COUNTS, (int(v) for v in cnt)))
+        self.ws = None
+
+    # ------------------------------------------------------------------
+    def _call(self, name, *args):
+        st = getattr(self.lib, name)(self.h, *args)
+        if st != DGH_OK:
+            msg = self.lib.dgh_last_error(self.h).decode()
+            raise DghError(f"{name}: {STATUS.get(st, st)}: {msg}")
+
+    def shapes(self):
+        k = self.counts
+        P = k["P"]
+        return {
+            "q3": (k["K"], 4, k["Np"]), "res3": (k["K"], 4, k["Np"]),
+            "q2": (k["Ktri"], P, 3, k["Np2"]), "res2": (k["Ktri"], P, 3, k["Np2"]),
+            "qb3": (k["Ktri"], k["Np2"]), "q0_3": (k["Ktri"], k["Np2"]),
+            "q1": (k["Klin"], P * P, 2, k["Np1"]), "res1": (k["Klin"], P * P, 2, k["Np1"]),
+            "qb2": (k["Klin"], 2, P, k["Np1"]), "q0_2": (k["Klin"], 2, P, k["Np1"]),
+            "qb1": (k["Kpnt"], 3, P * P),
+        }
+
+    def node_coords(self):
+        out = np.empty((self.counts["K"], self.counts["Np"], 3))
+        self._call("dgh_node_coords", _ptr(out))
+        return out
+
+    def workspace_size(self):
+        n = C.c_size_t()
+        self._call("dgh_workspace_size", C.byref(n))
+        return n.value
+
+    def bind(self, stream=None):
+        """Allocates the workspace as a torch uint8 tensor on the device and
+        binds it with the given (or current) torch stream."""
+        import torch
+        nbytes = self.workspace_size()
+        dev = torch.device("cuda", self.device)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._call("dgh_bind_workspace", C.c_void_p(base + off), C.c_size_t(nbytes),
+                   C.c_void_p(self.stream.cuda_stream))
+        return self
+
+    def set_state(self, arrays=None, shot=0):
+        arrays = arrays or {}
+        shapes = self.shapes()
+        keep = []
+        ptrs = (C.c_void_p * len(ARRAYS))()
+        for i, name in enumerate(ARRAYS):
+            if name in arrays and arrays[name] is not None:
+                a = np.ascontiguousarray(arrays[name], dtype=np.float64)
+                if a.shape != shapes[name]:
+                    raise ValueError(f"{name}: shape {a.shape} != {shapes[name]}")
+                keep.append(a)
+                ptrs[i] = a.ctypes.data
+            else:
+                ptrs[i] = None
+        self._call("dgh_set_state", shot, C.cast(ptrs, C.c_void_p))
+
+    def read_fields(self, names=None, shot=0):
+        shapes = self.shapes()
+        names = ARRAYS if names is None else names
+        out = {n: np.empty(shapes[n]) for n in names}
+        ptrs = (C.c_void_p * len(ARRAYS))()
+        for i, name in enumerate(ARRAYS):
+            ptrs[i] = out[name].ctypes.data if name in out else None
+        self._call("dgh_read_fields", shot, C.cast(ptrs, C.c_void_p))
+        return out
+
+    def set_source(self, xs, f0, t0, amp=1.0, shot=0):
+        x = np.ascontiguousarray(xs, dtype=np.float64)
+        self._call("dgh_set_source", shot, _ptr(x), float(f0), float(t0), float(amp))
+
+    def step(self, n_steps, dt, t_start=0.0):
+        self._call("dgh_step", int(n_steps), float(dt), float(t_start))
+
+    def energy(self, shot=0):
+        e = C.c_double()
+        self._call("dgh_energy", shot, C.byref(e))
+        return e.value
+
+    def kernel_timing(self, enable):
+        self._call("dgh_kernel_timing", 1 if enable else 0)
+
+    def kernel_time(self, level=3):
+        t = C.c_double()
+        n = C.c_longlong()
+        self._call("dgh_kernel_time", level, C.byref(t), C.byref(n))
+        return t.value, n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dgh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

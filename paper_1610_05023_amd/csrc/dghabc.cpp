@@ -1,0 +1,788 @@
+// C ABI of the time stepper (include/dghabc.h): setup on the host, device
+// data inside one caller-owned workspace, and the stage loop of Algorithm 1.
+#include "dghabc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "habc.hpp"
+#include "levels.hpp"
+#include "mesh.hpp"
+
+namespace {
+
+// Carpenter & Kennedy (1994) five-stage fourth-order 2N-storage coefficients.
+const double kA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                      -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                      1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                      2277821191437.0 / 14882151754819.0};
+const double kC[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                      2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
+
+enum Stage { S_CREATED = 0, S_MESH, S_ORDER, S_HABC, S_MATERIAL, S_BOUND };
+
+struct Region {
+  size_t off = 0, bytes = 0;
+};
+
+struct Layout {
+  size_t total = 0;
+  Region q3[2], res3, geo3, zn3, nbr3, ops3, fmask3, fmap3, mass3, J3, esum;
+  Region q2[2], res2, qb3, q03, geo2, info2, tetnode2, nbrnode2, ops2, fmask2, gamma;
+  Region q1[2], res1, qb2, q02, geo1, info1, trinode1, ops1, cji, cij, G, H;
+  Region qb1, info0, nrm0, T, srcw;
+  Region* add(Region& r, size_t bytes) {
+    r.off = total;
+    r.bytes = bytes;
+    total += (bytes + 255) / 256 * 256;
+    return &r;
+  }
+};
+
+}  // namespace
+
+struct dgh_ctx {
+  int device = 0, precision = 0, n_shots = 1;
+  int stage = S_CREATED;
+  std::string err;
+  dgh::Mesh mesh;
+  int N = 0, P = 0;
+  std::vector<double> gamma_in;
+  bool gamma_given = false;
+  dgh::HabcConsts habc;
+  std::vector<double> rho, c;
+  Layout lay;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int cur = 0;
+  int ntile = 0;
+  // source
+  int src_elem = -1;
+  double f0 = 0, t0 = 0, amp = 0;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;   // pairs (start, stop) per timed launch
+  size_t ev_used = 0;
+  // host copies of device-layout constants (kept for tests and re-uploads)
+  dgh::Lvl3 L3{};
+  dgh::Lvl2 L2{};
+  dgh::Lvl1 L1{};
+  dgh::Lvl0 L0{};
+};
+
+namespace {
+
+dgh_status fail(dgh_ctx* c, dgh_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+dgh_status hipfail(dgh_ctx* c, hipError_t e, const char* where) {
+  return fail(c, DGH_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHECK(ctx, call)                                   \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return hipfail(ctx, e_, #call);     \
+  } while (0)
+
+template <class T>
+T* dptr(dgh_ctx* c, const Region& r) {
+  return reinterpret_cast<T*>(c->ws + r.off);
+}
+
+// Builds the device-layout arrays on the host.
+struct HostArrays {
+  std::vector<double> geo3, zn3, ops3, mass3, J3;
+  std::vector<int> nbr3, fmask3, fmap3;
+  std::vector<double> geo2, ops2;
+  std::vector<int> info2, tetnode2, nbrnode2, fmask2;
+  std::vector<double> geo1, ops1;
+  std::vector<int> info1, trinode1;
+  std::vector<int> info0;
+  std::vector<double> nrm0;
+  bool map_ok = true;
+};
+
+void build_host_arrays(dgh_ctx* c, HostArrays& h) {
+  const dgh::Mesh& m = c->mesh;
+  const int K = m.K, Np = m.tet.Np, Nfp = m.tet.Nfp, nt = c->ntile;
+  const int T = dgh::kTile;
+  // ---- 3D
+  h.geo3.assign((size_t)nt * 12 * T, 0.0);
+  h.zn3.assign((size_t)nt * 4 * T, 1.0);
+  h.nbr3.assign((size_t)nt * 4 * T, -1 - 1);  // padding: ABC boundary
+  h.J3.assign((size_t)nt * T, 0.0);
+  for (int slot = 0; slot < nt * T; ++slot) {
+    const int tile = slot / T, es = slot % T;
+    double* g = &h.geo3[(size_t)tile * 12 * T + es];
+    if (slot >= K) {  // benign padding geometry, never written back
+      g[0] = g[4 * T] = g[8 * T] = 1.0;
+      g[9 * T] = g[10 * T] = g[11 * T] = 1.0;
+      continue;
+    }
+    const int e = slot;
+    for (int k = 0; k < 9; ++k) g[k * T] = m.geo[9 * e + k];
+    g[9 * T] = 1.0 / c->rho[e];
+    g[10 * T] = c->rho[e] * c->c[e] * c->c[e];
+    g[11 * T] = c->rho[e] * c->c[e];
+    h.J3[slot] = m.J[e];
+    for (int f = 0; f < 4; ++f) {
+      const size_t o = ((size_t)tile * 4 + f) * T + es;
+      const int e2 = m.EToE[4 * e + f];
+      if (e2 >= 0) {
+        h.nbr3[o] = (e2 << 5) | (m.EToF[4 * e + f] << 3) | m.perm[4 * e + f];
+        h.zn3[o] = c->rho[e2] * c->c[e2];
+      } else {
+        const int df = m.bface[4 * e + f];
+        const int bc = m.face_bc[df];
+        int code = 0;
+        if (bc == dgh::BC_HABC) {
+          const int t = m.face_tri[4 * e + f];
+          // permutation taking this face's vertices to the sorted triangle vertices
+          const int* tv = &m.tri_verts[3 * t];
+          int q[3];
+          for (int k = 0; k < 3; ++k) {
+            const int gv = m.EToV[4 * e + dgh::kFaceVerts[f][k]];
+            q[k] = (int)(std::find(tv, tv + 3, gv) - tv);
+          }
+          static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
+                                          {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+          int p = 0;
+          for (int k = 0; k < 6; ++k)
+            if (perms[k][0] == q[0] && perms[k][1] == q[1] && perms[k][2] == q[2]) p = k;
+          code = (t << 5) | (p << 2) | 0;
+          for (int i = 0; i < Nfp; ++i)
+            if (m.fmap[((f * 4 + 0) * 6 + p) * Nfp + i] != m.facenode_trinode[t * Nfp + i])
+              h.map_ok = false;
+        } else {
+          code = bc == dgh::BC_DIRICHLET ? 2 : 1;
+        }
+        h.nbr3[o] = -1 - code;
+        h.zn3[o] = c->rho[e] * c->c[e];
+      }
+    }
+  }
+  h.ops3.clear();
+  h.ops3.insert(h.ops3.end(), m.tet.Dr.begin(), m.tet.Dr.end());
+  h.ops3.insert(h.ops3.end(), m.tet.Ds.begin(), m.tet.Ds.end());
+  h.ops3.insert(h.ops3.end(), m.tet.Dt.begin(), m.tet.Dt.end());
+  h.ops3.insert(h.ops3.end(), m.tet.LIFT.begin(), m.tet.LIFT.end());
+  h.mass3 = m.tet.Mass;
+  h.fmask3 = m.tet.Fmask;
+  h.fmap3 = m.fmap;
+  (void)Np;
+  // ---- 2D
+  const int Kt = m.Ktri, Np2 = m.tri.Np, Nfp2 = m.tri.Nfp;
+  h.geo2.assign((size_t)Kt * 8, 0.0);
+  h.info2.assign((size_t)Kt * 8, 0);
+  h.tetnode2 = m.tri_tetnode;
+  h.nbrnode2.assign((size_t)Kt * 3 * Nfp2, 0);
+  for (int t = 0; t < Kt; ++t) {
+    const int e = m.tri_elem[t];
+    for (int k = 0; k < 4; ++k) h.geo2[t * 8 + k] = m.tri_geo[4 * t + k];
+    h.geo2[t * 8 + 4] = 1.0 / c->rho[e];
+    h.geo2[t * 8 + 5] = c->rho[e] * c->c[e] * c->c[e];
+    h.geo2[t * 8 + 6] = c->rho[e] * c->c[e];
+    h.info2[t * 8 + 0] = e;
+    h.info2[t * 8 + 1] = m.tri_dface[t] / 2;
+    h.info2[t * 8 + 2] = (m.tri_dface[t] % 2) ? 1 : -1;
+    for (int f = 0; f < 3; ++f) {
+      const int t2 = m.tri_EToE[3 * t + f];
+      int code;
+      if (t2 >= 0) {
+        code = t2;
+        for (int k = 0; k < Nfp2; ++k)
+          h.nbrnode2[(t * 3 + f) * Nfp2 + k] = m.tri_nbr_node[(3 * t + f) * Nfp2 + k];
+      } else {
+        const int l = m.tri_edge_line[3 * t + f];
+        if (l >= 0) {
+          code = -1 - ((l << 3) | (m.tri_edge_side[3 * t + f] << 2) | 0);
+          for (int k = 0; k < Nfp2; ++k)
+            h.nbrnode2[(t * 3 + f) * Nfp2 + k] = m.tri_edge_linenode[(3 * t + f) * Nfp2 + k];
+        } else {
+          const int bc = m.face_bc[m.tri_bdface[3 * t + f]];
+          code = -1 - (bc == dgh::BC_DIRICHLET ? 2 : 1);
+        }
+      }
+      h.info2[t * 8 + 3 + f] = code;
+    }
+  }
+  h.ops2.clear();
+  h.ops2.insert(h.ops2.end(), m.tri.Dr.begin(), m.tri.Dr.end());
+  h.ops2.insert(h.ops2.end(), m.tri.Ds.begin(), m.tri.Ds.end());
+  h.ops2.insert(h.ops2.end(), m.tri.LIFT.begin(), m.tri.LIFT.end());
+  h.fmask2 = m.tri.Fmask;
+  (void)Np2;
+  // ---- 1D
+  const int Kl = m.Klin, Np1 = m.line.Np;
+  h.geo1.assign((size_t)Kl * 4, 0.0);
+  h.info1.assign((size_t)Kl * 8, 0);
+  h.trinode1 = m.lin_trinode;
+  for (int l = 0; l < Kl; ++l) {
+    const int tA = m.lin_tri[2 * l];
+    const int e = m.tri_elem[tA];
+    h.geo1[l * 4 + 0] = m.lin_rx[l];
+    h.geo1[l * 4 + 1] = 1.0 / c->rho[e];
+    h.geo1[l * 4 + 2] = c->rho[e] * c->c[e] * c->c[e];
+    h.geo1[l * 4 + 3] = c->rho[e] * c->c[e];
+    const int de = m.lin_dedge[l];
+    for (int side = 0; side < 2; ++side) {
+      const int t = m.lin_tri[2 * l + side];
+      const int other = dgh::kDomainEdges[de][1 - side];
+      const int ax = other / 2;
+      const int comp = 1 + (m.tri_axes[2 * t] == ax ? 0 : 1);
+      h.info1[l * 8 + side] = t;
+      h.info1[l * 8 + 2 + side] = (other % 2) ? comp : -comp;
+    }
+    const double sgn = m.lin_rx[l] > 0 ? 1.0 : -1.0;
+    for (int end = 0; end < 2; ++end) {
+      int code;
+      const int l2 = m.lin_EToE[2 * l + end];
+      if (l2 >= 0) {
+        code = (l2 << 1) | m.lin_EToF[2 * l + end];
+      } else if (m.lin_corner[2 * l + end] >= 0) {
+        code = -1 - ((m.lin_corner[2 * l + end] << 4) | (m.lin_corner_slot[2 * l + end] << 2) | 0);
+      } else {
+        code = -1 - (m.lin_endbc[2 * l + end] == dgh::BC_DIRICHLET ? 2 : 1);
+      }
+      h.info1[l * 8 + 4 + end] = code;
+      h.info1[l * 8 + 6 + end] = (int)(end ? sgn : -sgn);
+    }
+  }
+  h.ops1 = m.line.Dr;
+  h.ops1.insert(h.ops1.end(), m.line.LIFT.begin(), m.line.LIFT.end());
+  (void)Np1;
+  // ---- 0D
+  h.info0.assign((size_t)m.Kpnt * 6, 0);
+  h.nrm0 = m.pnt_nrm;
+  for (int p = 0; p < m.Kpnt; ++p)
+    for (int a = 0; a < 3; ++a) {
+      h.info0[(p * 3 + a) * 2] = m.pnt_line[3 * p + a];
+      h.info0[(p * 3 + a) * 2 + 1] = m.pnt_end[3 * p + a];
+    }
+}
+
+void compute_layout(dgh_ctx* c) {
+  const dgh::Mesh& m = c->mesh;
+  Layout& L = c->lay;
+  L = Layout{};
+  const int Np = m.tet.Np, Nfp = m.tet.Nfp, nt = c->ntile, T = dgh::kTile, P = c->P;
+  const size_t d = sizeof(double), i4 = sizeof(int);
+  const size_t s3 = (size_t)nt * 4 * Np * T * d;
+  L.add(L.q3[0], s3);
+  L.add(L.q3[1], s3);
+  L.add(L.res3, s3);
+  L.add(L.geo3, (size_t)nt * 12 * T * d);
+  L.add(L.zn3, (size_t)nt * 4 * T * d);
+  L.add(L.nbr3, (size_t)nt * 4 * T * i4);
+  L.add(L.ops3, (size_t)(3 * Np * Np + Np * 4 * Nfp) * d);
+  L.add(L.fmask3, (size_t)4 * Nfp * i4);
+  L.add(L.fmap3, (size_t)96 * Nfp * i4);
+  L.add(L.mass3, (size_t)Np * Np * d);
+  L.add(L.J3, (size_t)nt * T * d);
+  L.add(L.esum, (size_t)nt * d);
+  const int Kt = m.Ktri, Np2 = m.tri.Np, Nfp2 = m.tri.Nfp;
+  const size_t s2 = (size_t)std::max(1, Kt * P * 3 * Np2) * d;
+  L.add(L.q2[0], s2);
+  L.add(L.q2[1], s2);
+  L.add(L.res2, s2);
+  L.add(L.qb3, (size_t)std::max(1, Kt * Np2) * d);
+  L.add(L.q03, (size_t)std::max(1, Kt * Np2) * d);
+  L.add(L.geo2, (size_t)std::max(1, Kt * 8) * d);
+  L.add(L.info2, (size_t)std::max(1, Kt * 8) * i4);
+  L.add(L.tetnode2, (size_t)std::max(1, Kt * Np2) * i4);
+  L.add(L.nbrnode2, (size_t)std::max(1, Kt * 3 * Nfp2) * i4);
+  L.add(L.ops2, (size_t)(2 * Np2 * Np2 + Np2 * 3 * Nfp2) * d);
+  L.add(L.fmask2, (size_t)3 * Nfp2 * i4);
+  L.add(L.gamma, (size_t)std::max(1, P) * d);
+  const int Kl = m.Klin, Np1 = m.line.Np;
+  const size_t s1 = (size_t)std::max(1, Kl * P * P * 2 * Np1) * d;
+  L.add(L.q1[0], s1);
+  L.add(L.q1[1], s1);
+  L.add(L.res1, s1);
+  L.add(L.qb2, (size_t)std::max(1, Kl * 2 * P * Np1) * d);
+  L.add(L.q02, (size_t)std::max(1, Kl * 2 * P * Np1) * d);
+  L.add(L.geo1, (size_t)std::max(1, Kl * 4) * d);
+  L.add(L.info1, (size_t)std::max(1, Kl * 8) * i4);
+  L.add(L.trinode1, (size_t)std::max(1, Kl * 2 * Np1) * i4);
+  L.add(L.ops1, (size_t)(Np1 * Np1 + 2 * Np1) * d);
+  L.add(L.cji, (size_t)std::max(1, P * P) * d);
+  L.add(L.cij, (size_t)std::max(1, P * P) * d);
+  L.add(L.G, (size_t)std::max(1, 4 * P * P) * d);
+  L.add(L.H, (size_t)std::max(1, 4 * P * P) * d);
+  L.add(L.qb1, (size_t)std::max(1, m.Kpnt * 3 * P * P) * d);
+  L.add(L.info0, (size_t)std::max(1, m.Kpnt * 6) * i4);
+  L.add(L.nrm0, (size_t)std::max(1, m.Kpnt * 3) * d);
+  L.add(L.T, (size_t)std::max(1, 9 * P * P * P * P) * d);
+  L.add(L.srcw, (size_t)Np * d);
+}
+
+template <class V>
+hipError_t upload(dgh_ctx* c, const Region& r, const V& v) {
+  if (v.empty()) return hipSuccess;
+  const size_t b = v.size() * sizeof(v[0]);
+  if (b > r.bytes) return hipErrorInvalidValue;
+  return hipMemcpy(c->ws + r.off, v.data(), b, hipMemcpyHostToDevice);
+}
+
+void fill_levels(dgh_ctx* c) {
+  const dgh::Mesh& m = c->mesh;
+  const Layout& L = c->lay;
+  dgh::Lvl3& a = c->L3;
+  a.K = m.K;
+  a.ntile = c->ntile;
+  a.N = m.N;
+  a.Np = m.tet.Np;
+  a.Nfp = m.tet.Nfp;
+  a.ops = dptr<double>(c, L.ops3);
+  a.fmask = dptr<int>(c, L.fmask3);
+  a.fmap = dptr<int>(c, L.fmap3);
+  a.geo = dptr<double>(c, L.geo3);
+  a.zn = dptr<double>(c, L.zn3);
+  a.nbr = dptr<int>(c, L.nbr3);
+  dgh::Lvl2& b = c->L2;
+  b.Kt = m.Ktri;
+  b.P = c->P;
+  b.Np = m.tri.Np;
+  b.Nfp = m.tri.Nfp;
+  b.invM = 1.0 / (2.0 * c->P + 1.0);
+  b.ops = dptr<double>(c, L.ops2);
+  b.fmask = dptr<int>(c, L.fmask2);
+  b.geo = dptr<double>(c, L.geo2);
+  b.info = dptr<int>(c, L.info2);
+  b.tetnode = dptr<int>(c, L.tetnode2);
+  b.nbrnode = dptr<int>(c, L.nbrnode2);
+  b.gamma = dptr<double>(c, L.gamma);
+  dgh::Lvl1& d = c->L1;
+  d.Kl = m.Klin;
+  d.P = c->P;
+  d.Np = m.line.Np;
+  d.invM = b.invM;
+  d.ops = dptr<double>(c, L.ops1);
+  d.geo = dptr<double>(c, L.geo1);
+  d.info = dptr<int>(c, L.info1);
+  d.trinode = dptr<int>(c, L.trinode1);
+  d.gamma = b.gamma;
+  d.Cji = dptr<double>(c, L.cji);
+  d.Cij = dptr<double>(c, L.cij);
+  d.G = dptr<double>(c, L.G);
+  d.H = dptr<double>(c, L.H);
+  dgh::Lvl0& z = c->L0;
+  z.Kp = m.Kpnt;
+  z.P = c->P;
+  z.info = dptr<int>(c, L.info0);
+  z.nrm = dptr<double>(c, L.nrm0);
+  z.T = dptr<double>(c, L.T);
+}
+
+// canonical [K][4][Np] <-> device [tile][4][Np][16]
+void to_tiles(const double* src, double* dst, int K, int Np, int ntile) {
+  const int T = dgh::kTile;
+  std::fill(dst, dst + (size_t)ntile * 4 * Np * T, 0.0);
+  for (int e = 0; e < K; ++e)
+    for (int f = 0; f < 4; ++f)
+      for (int n = 0; n < Np; ++n)
+        dst[(((size_t)(e / T) * 4 + f) * Np + n) * T + (e % T)] = src[((size_t)e * 4 + f) * Np + n];
+}
+
+void from_tiles(const double* src, double* dst, int K, int Np) {
+  const int T = dgh::kTile;
+  for (int e = 0; e < K; ++e)
+    for (int f = 0; f < 4; ++f)
+      for (int n = 0; n < Np; ++n)
+        dst[((size_t)e * 4 + f) * Np + n] = src[(((size_t)(e / T) * 4 + f) * Np + n) * T + (e % T)];
+}
+
+}  // namespace
+
+extern "C" {
+
+dgh_status dgh_create(dgh_ctx** out, int device, int precision, int n_shots) {
+  if (!out) return DGH_EINVAL;
+  *out = nullptr;
+  if (precision != DGH_FP64 || n_shots != 1 || device < 0) return DGH_EINVAL;
+  dgh_ctx* c = new (std::nothrow) dgh_ctx();
+  if (!c) return DGH_ENOMEM;
+  c->device = device;
+  c->precision = precision;
+  c->n_shots = n_shots;
+  *out = c;
+  return DGH_OK;
+}
+
+dgh_status dgh_upload_mesh(dgh_ctx* c, int Nv, const double* VX, int K, const int* EToV,
+                           const double* box, const int* periodic) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage >= S_BOUND) return fail(c, DGH_ESTATE, "mesh after bind");
+  if (Nv <= 0 || K <= 0 || !VX || !EToV || !box) return fail(c, DGH_EINVAL, "bad mesh arguments");
+  if (K >= (1 << 26)) return fail(c, DGH_EINVAL, "too many elements");
+  dgh::Mesh& m = c->mesh;
+  m = dgh::Mesh{};
+  m.Nv = Nv;
+  m.K = K;
+  m.VX.assign(VX, VX + 3 * (size_t)Nv);
+  m.EToV.assign(EToV, EToV + 4 * (size_t)K);
+  for (int d = 0; d < 3; ++d) {
+    m.lo[d] = box[d];
+    m.hi[d] = box[3 + d];
+    if (!(m.hi[d] > m.lo[d])) return fail(c, DGH_EINVAL, "empty box");
+    m.periodic[d] = periodic ? (periodic[d] != 0) : 0;
+  }
+  c->stage = S_MESH;
+  return DGH_OK;
+}
+
+dgh_status dgh_set_order(dgh_ctx* c, int N) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_MESH || c->stage >= S_BOUND) return fail(c, DGH_ESTATE, "set_order out of order");
+  if (N < 1 || N > 6) return fail(c, DGH_EINVAL, "N must be in 1..6");
+  c->N = N;
+  c->stage = S_ORDER;
+  return DGH_OK;
+}
+
+dgh_status dgh_set_habc(dgh_ctx* c, int P, const double* gamma, const int* face_bc) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_ORDER || c->stage >= S_BOUND) return fail(c, DGH_ESTATE, "set_habc out of order");
+  if (P < 0 || P > 12) return fail(c, DGH_EINVAL, "P must be in 0..12");
+  dgh::Mesh& m = c->mesh;
+  m.N = c->N;
+  for (int f = 0; f < 6; ++f) {
+    const int bc = face_bc ? face_bc[f] : DGH_BC_HABC;
+    if (bc < 0 || bc > 3) return fail(c, DGH_EINVAL, "bad face_bc");
+    m.face_bc[f] = bc;
+  }
+  for (int d = 0; d < 3; ++d)
+    if ((m.face_bc[2 * d] == DGH_BC_PERIODIC) != (m.face_bc[2 * d + 1] == DGH_BC_PERIODIC))
+      return fail(c, DGH_EINVAL, "periodic must pair both faces of an axis");
+    else if (m.face_bc[2 * d] == DGH_BC_PERIODIC)
+      m.periodic[d] = 1;
+  const std::string r = dgh::build_mesh(m);
+  if (!r.empty()) return fail(c, DGH_EINVAL, r);
+  if (!dgh::build_habc(P, gamma, c->habc)) return fail(c, DGH_EINVAL, "bad HABC coefficients");
+  c->P = P;
+  c->ntile = (m.K + dgh::kTile - 1) / dgh::kTile;
+  c->stage = S_HABC;
+  return DGH_OK;
+}
+
+dgh_status dgh_set_material(dgh_ctx* c, const double* rho, const double* cc) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_HABC || c->stage >= S_BOUND) return fail(c, DGH_ESTATE, "set_material out of order");
+  if (!rho || !cc) return fail(c, DGH_EINVAL, "null material");
+  const int K = c->mesh.K;
+  for (int e = 0; e < K; ++e)
+    if (!(rho[e] > 0) || !(cc[e] > 0) || !std::isfinite(rho[e]) || !std::isfinite(cc[e]))
+      return fail(c, DGH_EINVAL, "materials must be positive and finite");
+  c->rho.assign(rho, rho + K);
+  c->c.assign(cc, cc + K);
+  c->stage = S_MATERIAL;
+  return DGH_OK;
+}
+
+dgh_status dgh_counts(const dgh_ctx* c, int* out) {
+  if (!c || !out) return DGH_EINVAL;
+  if (c->stage < S_HABC) return DGH_ESTATE;
+  const dgh::Mesh& m = c->mesh;
+  out[DGH_C_K] = m.K;
+  out[DGH_C_KTRI] = m.Ktri;
+  out[DGH_C_KLIN] = m.Klin;
+  out[DGH_C_KPNT] = m.Kpnt;
+  out[DGH_C_NP] = m.tet.Np;
+  out[DGH_C_NP2] = m.tri.Np;
+  out[DGH_C_NP1] = m.line.Np;
+  out[DGH_C_P] = c->P;
+  out[DGH_C_N] = c->N;
+  out[DGH_C_NSHOTS] = c->n_shots;
+  return DGH_OK;
+}
+
+dgh_status dgh_node_coords(const dgh_ctx* c, double* out) {
+  if (!c || !out) return DGH_EINVAL;
+  if (c->stage < S_HABC) return DGH_ESTATE;
+  const dgh::Mesh& m = c->mesh;
+  for (int e = 0; e < m.K; ++e)
+    for (int n = 0; n < m.tet.Np; ++n) m.node_xyz(e, n, out + ((size_t)e * m.tet.Np + n) * 3);
+  return DGH_OK;
+}
+
+dgh_status dgh_workspace_size(dgh_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return DGH_EINVAL;
+  if (c->stage < S_MATERIAL) return fail(c, DGH_ESTATE, "workspace_size before set_material");
+  compute_layout(c);
+  *bytes = c->lay.total;
+  return DGH_OK;
+}
+
+dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_MATERIAL) return fail(c, DGH_ESTATE, "bind before set_material");
+  compute_layout(c);
+  if (!dev || bytes < c->lay.total) return fail(c, DGH_ENOMEM, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(c, DGH_EINVAL, "workspace not 256-byte aligned");
+  HIPCHECK(c, hipSetDevice(c->device));
+  c->ws = static_cast<char*>(dev);
+  c->stream = static_cast<hipStream_t>(stream);
+  HostArrays h;
+  build_host_arrays(c, h);
+  if (!h.map_ok) return fail(c, DGH_EINVAL, "tet face to triangle node map mismatch");
+  const Layout& L = c->lay;
+  HIPCHECK(c, hipMemsetAsync(c->ws, 0, L.total, c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  HIPCHECK(c, upload(c, L.geo3, h.geo3));
+  HIPCHECK(c, upload(c, L.zn3, h.zn3));
+  HIPCHECK(c, upload(c, L.nbr3, h.nbr3));
+  HIPCHECK(c, upload(c, L.ops3, h.ops3));
+  HIPCHECK(c, upload(c, L.fmask3, h.fmask3));
+  HIPCHECK(c, upload(c, L.fmap3, h.fmap3));
+  HIPCHECK(c, upload(c, L.mass3, h.mass3));
+  HIPCHECK(c, upload(c, L.J3, h.J3));
+  HIPCHECK(c, upload(c, L.geo2, h.geo2));
+  HIPCHECK(c, upload(c, L.info2, h.info2));
+  HIPCHECK(c, upload(c, L.tetnode2, h.tetnode2));
+  HIPCHECK(c, upload(c, L.nbrnode2, h.nbrnode2));
+  HIPCHECK(c, upload(c, L.ops2, h.ops2));
+  HIPCHECK(c, upload(c, L.fmask2, h.fmask2));
+  HIPCHECK(c, upload(c, L.gamma, c->habc.gamma));
+  HIPCHECK(c, upload(c, L.geo1, h.geo1));
+  HIPCHECK(c, upload(c, L.info1, h.info1));
+  HIPCHECK(c, upload(c, L.trinode1, h.trinode1));
+  HIPCHECK(c, upload(c, L.ops1, h.ops1));
+  HIPCHECK(c, upload(c, L.cji, c->habc.Cji));
+  HIPCHECK(c, upload(c, L.cij, c->habc.Cij));
+  HIPCHECK(c, upload(c, L.G, c->habc.G));
+  HIPCHECK(c, upload(c, L.H, c->habc.H));
+  HIPCHECK(c, upload(c, L.info0, h.info0));
+  HIPCHECK(c, upload(c, L.nrm0, h.nrm0));
+  HIPCHECK(c, upload(c, L.T, c->habc.T));
+  fill_levels(c);
+  c->cur = 0;
+  c->src_elem = -1;
+  c->stage = S_BOUND;
+  return DGH_OK;
+}
+
+dgh_status dgh_set_state(dgh_ctx* c, int shot, const double* const* arr) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "set_state before bind");
+  if (shot != 0) return fail(c, DGH_EINVAL, "shot out of range");
+  const dgh::Mesh& m = c->mesh;
+  const Layout& L = c->lay;
+  const int Np = m.tet.Np;
+  const int cur = c->cur;
+  std::vector<double> buf((size_t)c->ntile * 4 * Np * dgh::kTile);
+  std::vector<double> zero((size_t)m.K * 4 * Np, 0.0);
+  for (int which : {DGH_Q3, DGH_RES3}) {
+    const double* src = (arr && arr[which]) ? arr[which] : zero.data();
+    to_tiles(src, buf.data(), m.K, Np, c->ntile);
+    const Region& r = which == DGH_Q3 ? L.q3[cur] : L.res3;
+    HIPCHECK(c, hipMemcpy(c->ws + r.off, buf.data(), r.bytes, hipMemcpyHostToDevice));
+  }
+  struct Item { int idx; const Region* r; size_t n; };
+  const int P = c->P;
+  const Item items[] = {
+      {DGH_Q2, &L.q2[cur], (size_t)m.Ktri * P * 3 * m.tri.Np},
+      {DGH_RES2, &L.res2, (size_t)m.Ktri * P * 3 * m.tri.Np},
+      {DGH_QB3, &L.qb3, (size_t)m.Ktri * m.tri.Np},
+      {DGH_Q03, &L.q03, (size_t)m.Ktri * m.tri.Np},
+      {DGH_Q1, &L.q1[cur], (size_t)m.Klin * P * P * 2 * m.line.Np},
+      {DGH_RES1, &L.res1, (size_t)m.Klin * P * P * 2 * m.line.Np},
+      {DGH_QB2, &L.qb2, (size_t)m.Klin * 2 * P * m.line.Np},
+      {DGH_Q02, &L.q02, (size_t)m.Klin * 2 * P * m.line.Np},
+      {DGH_QB1, &L.qb1, (size_t)m.Kpnt * 3 * P * P},
+  };
+  for (const Item& it : items) {
+    if (it.n == 0) continue;
+    char* dst = c->ws + it.r->off;
+    if (arr && arr[it.idx]) {
+      HIPCHECK(c, hipMemcpy(dst, arr[it.idx], it.n * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+      HIPCHECK(c, hipMemset(dst, 0, it.n * sizeof(double)));
+    }
+  }
+  HIPCHECK(c, hipDeviceSynchronize());
+  return DGH_OK;
+}
+
+dgh_status dgh_read_fields(dgh_ctx* c, int shot, double* const* arr) {
+  if (!c || !arr) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "read before bind");
+  if (shot != 0) return fail(c, DGH_EINVAL, "shot out of range");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  const dgh::Mesh& m = c->mesh;
+  const Layout& L = c->lay;
+  const int Np = m.tet.Np, cur = c->cur, P = c->P;
+  std::vector<double> buf((size_t)c->ntile * 4 * Np * dgh::kTile);
+  for (int which : {DGH_Q3, DGH_RES3}) {
+    if (!arr[which]) continue;
+    const Region& r = which == DGH_Q3 ? L.q3[cur] : L.res3;
+    HIPCHECK(c, hipMemcpy(buf.data(), c->ws + r.off, r.bytes, hipMemcpyDeviceToHost));
+    from_tiles(buf.data(), arr[which], m.K, Np);
+  }
+  struct Item { int idx; const Region* r; size_t n; };
+  const Item items[] = {
+      {DGH_Q2, &L.q2[cur], (size_t)m.Ktri * P * 3 * m.tri.Np},
+      {DGH_RES2, &L.res2, (size_t)m.Ktri * P * 3 * m.tri.Np},
+      {DGH_QB3, &L.qb3, (size_t)m.Ktri * m.tri.Np},
+      {DGH_Q03, &L.q03, (size_t)m.Ktri * m.tri.Np},
+      {DGH_Q1, &L.q1[cur], (size_t)m.Klin * P * P * 2 * m.line.Np},
+      {DGH_RES1, &L.res1, (size_t)m.Klin * P * P * 2 * m.line.Np},
+      {DGH_QB2, &L.qb2, (size_t)m.Klin * 2 * P * m.line.Np},
+      {DGH_Q02, &L.q02, (size_t)m.Klin * 2 * P * m.line.Np},
+      {DGH_QB1, &L.qb1, (size_t)m.Kpnt * 3 * P * P},
+  };
+  for (const Item& it : items)
+    if (arr[it.idx] && it.n)
+      HIPCHECK(c, hipMemcpy(arr[it.idx], c->ws + it.r->off, it.n * sizeof(double), hipMemcpyDeviceToHost));
+  return DGH_OK;
+}
+
+dgh_status dgh_set_source(dgh_ctx* c, int shot, const double* xs, double f0, double t0, double amp) {
+  if (!c || !xs) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "set_source before bind");
+  if (shot != 0) return fail(c, DGH_EINVAL, "shot out of range");
+  if (amp == 0.0) {
+    c->src_elem = -1;
+    return DGH_OK;
+  }
+  const dgh::Mesh& m = c->mesh;
+  // the element whose smallest barycentric coordinate of xs is largest
+  int best = -1;
+  double bmin = -1e300, lam_best[3] = {0, 0, 0};
+  for (int e = 0; e < m.K; ++e) {
+    const double* g = &m.geo[9 * e];  // rows grad r, grad s, grad t
+    const double* v0 = &m.VX[3 * m.EToV[4 * e]];
+    double d[3] = {xs[0] - v0[0], xs[1] - v0[1], xs[2] - v0[2]};
+    // (r+1)/2 = grad r . d / 2 ... since x - v0 = sum_k (xi_k + 1)/2 (v_k - v0)
+    double lam[3];
+    for (int k = 0; k < 3; ++k) lam[k] = 0.5 * (g[3 * k] * d[0] + g[3 * k + 1] * d[1] + g[3 * k + 2] * d[2]);
+    const double l0 = 1.0 - lam[0] - lam[1] - lam[2];
+    const double mn = std::min(std::min(l0, lam[0]), std::min(lam[1], lam[2]));
+    if (mn > bmin) {
+      bmin = mn;
+      best = e;
+      for (int k = 0; k < 3; ++k) lam_best[k] = lam[k];
+    }
+  }
+  if (bmin < -1e-9) return fail(c, DGH_EINVAL, "source outside the mesh");
+  const int Np = m.tet.Np;
+  std::vector<double> psi(Np), w(Np, 0.0);
+  dgh::tet_basis_at(m.N, 2 * lam_best[0] - 1, 2 * lam_best[1] - 1, 2 * lam_best[2] - 1, psi.data());
+  for (int a = 0; a < Np; ++a) {
+    for (int k = 0; k < Np; ++k) w[a] += m.tet.V[a * Np + k] * psi[k];
+    w[a] /= m.J[best];
+  }
+  HIPCHECK(c, hipMemcpy(c->ws + c->lay.srcw.off, w.data(), Np * sizeof(double), hipMemcpyHostToDevice));
+  c->src_elem = best;
+  c->f0 = f0;
+  c->t0 = t0;
+  c->amp = amp;
+  return DGH_OK;
+}
+
+dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "step before bind");
+  if (n_steps < 0 || !(dt > 0) || !std::isfinite(t_start)) return fail(c, DGH_EINVAL, "bad step arguments");
+  const Layout& L = c->lay;
+  const double* srcw = dptr<double>(c, L.srcw);
+  for (int it = 0; it < n_steps; ++it) {
+    const double t = t_start + it * dt;
+    for (int s = 0; s < 5; ++s) {
+      const int o = c->cur, n = 1 - c->cur;
+      double S = 0.0;
+      if (c->src_elem >= 0) {
+        const double tau = t + kC[s] * dt - c->t0;
+        S = c->amp * tau * std::exp(-(M_PI * c->f0 * tau) * (M_PI * c->f0 * tau));
+      }
+      if (c->timing) {
+        if (c->ev_used + 2 > c->ev.size()) {
+          for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            HIPCHECK(c, hipEventCreate(&e));
+            c->ev.push_back(e);
+          }
+        }
+        HIPCHECK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+      }
+      HIPCHECK(c, dgh::launch_level3(c->L3, dptr<double>(c, L.q3[o]), dptr<double>(c, L.q3[n]),
+                                     dptr<double>(c, L.res3), dptr<double>(c, L.qb3), kA[s], kB[s],
+                                     dt, c->src_elem, srcw, S, c->stream));
+      if (c->timing) {
+        HIPCHECK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+        c->ev_used += 2;
+      }
+      HIPCHECK(c, dgh::launch_level2(c->L2, c->L3, dptr<double>(c, L.q2[o]), dptr<double>(c, L.q2[n]),
+                                     dptr<double>(c, L.res2), dptr<double>(c, L.qb2),
+                                     dptr<double>(c, L.qb3), dptr<double>(c, L.q03),
+                                     dptr<double>(c, L.q3[n]), kA[s], kB[s], dt, c->stream));
+      HIPCHECK(c, dgh::launch_level1(c->L1, c->L2, dptr<double>(c, L.q1[o]), dptr<double>(c, L.q1[n]),
+                                     dptr<double>(c, L.res1), dptr<double>(c, L.qb1),
+                                     dptr<double>(c, L.qb2), dptr<double>(c, L.q02),
+                                     dptr<double>(c, L.q2[n]), kA[s], kB[s], dt, c->stream));
+      HIPCHECK(c, dgh::launch_level0(c->L0, c->L1, dptr<double>(c, L.q1[n]), dptr<double>(c, L.qb1),
+                                     c->stream));
+      c->cur = n;
+    }
+  }
+  return DGH_OK;
+}
+
+dgh_status dgh_energy(dgh_ctx* c, int shot, double* e) {
+  if (!c || !e) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "energy before bind");
+  if (shot != 0) return fail(c, DGH_EINVAL, "shot out of range");
+  const Layout& L = c->lay;
+  HIPCHECK(c, dgh::launch_energy(c->L3, dptr<double>(c, L.q3[c->cur]), dptr<double>(c, L.mass3),
+                                 dptr<double>(c, L.J3), dptr<double>(c, L.esum), c->stream));
+  std::vector<double> part(c->ntile);
+  HIPCHECK(c, hipMemcpyAsync(part.data(), c->ws + L.esum.off, c->ntile * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  double s = 0.0;
+  for (double v : part) s += v;
+  *e = s;
+  return DGH_OK;
+}
+
+dgh_status dgh_kernel_timing(dgh_ctx* c, int enable) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "timing before bind");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  c->timing = enable != 0;
+  if (enable) c->ev_used = 0;
+  return DGH_OK;
+}
+
+dgh_status dgh_kernel_time(dgh_ctx* c, int level, double* total_ms, long long* launches) {
+  if (!c || !total_ms || !launches) return DGH_EINVAL;
+  if (level != 3) return fail(c, DGH_EINVAL, "only the 3D level is timed");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  double t = 0.0;
+  for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+    float ms = 0.f;
+    HIPCHECK(c, hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = (long long)(c->ev_used / 2);
+  return DGH_OK;
+}
+
+const char* dgh_last_error(const dgh_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void dgh_destroy(dgh_ctx* c) {
+  if (!c) return;
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

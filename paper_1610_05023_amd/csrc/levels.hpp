@@ -1,0 +1,89 @@
+// Device-side descriptions of the four levels of the multidimensional step
+// (volume, faces, edges, corners; Algorithm 1) and the launchers of their
+// kernels.  All pointers point into the caller-owned workspace.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace dgh {
+
+constexpr int kTile = 16;  // elements per tile of the 3D node-major layout
+
+// 3D level.  State layout [tile][field][node][16]; geometry [tile][12][16]:
+// rx ry rz sx sy sz tx ty tz 1/rho rho*c^2 rho*c; zn [tile][4][16] impedance
+// of the neighbour across each face; nbr [tile][4][16] face codes:
+//   >= 0 : (e2 << 5) | (f2 << 3) | perm      interior face
+//   <  0 : -1 - ((t << 5) | (perm << 2) | bc) boundary; bc 0 = HABC
+//          (t = triangle, perm = vertex permutation to it), 1 = ABC,
+//          2 = Dirichlet
+struct Lvl3 {
+  int K, ntile, N, Np, Nfp;
+  const double* ops;   // Dr | Ds | Dt (Np x Np each) | LIFT (Np x 4Nfp), row-major
+  const int* fmask;    // 4 x Nfp
+  const int* fmap;     // 4 x 4 x 6 x Nfp
+  const double* geo;
+  const double* zn;
+  const int* nbr;
+};
+
+// 2D level (faces).  q2 [Ktri][P][3][Np2]; geo [Ktri][8]: rx ry sx sy 1/rho
+// rho*c^2 rho*c (pad); info [Ktri][8]: owning tet, axis of the domain face,
+// sign of its outward normal (+-1), edge codes x3, (pad x2); edge code >= 0:
+// neighbour triangle; < 0: -1 - ((line << 3) | (side << 2) | bc), bc 0 =
+// HABC edge (a line), 1 = ABC, 2 = Dirichlet.  nbrnode [Ktri][3][Nfp2]: the
+// neighbour's node (interior edges) or the line node (HABC edges).
+struct Lvl2 {
+  int Kt, P, Np, Nfp;
+  double invM;
+  const double* ops;   // Dr2 | Ds2 | LIFT2 (Np x 3Nfp)
+  const int* fmask;    // 3 x Nfp
+  const double* geo;
+  const int* info;
+  const int* tetnode;  // [Ktri][Np2] node of the owning tet
+  const int* nbrnode;
+  const double* gamma; // P
+};
+
+// 1D level (edges).  q1 [Klin][P*P][2][Np1]; geo [Klin][4]: rx 1/rho
+// rho*c^2 rho*c; info [Klin][8]: tri side0, tri side1, velocity component of
+// the side-0 triangle along the side-1 face normal (1 or 2), same for side 1,
+// end codes x2, normal signs x2 (+-1 as int); end code >= 0: (l2 << 1) | end2;
+// < 0: -1 - ((corner << 4) | (slot << 2) | bc), bc 0 = corner, 1 = ABC,
+// 2 = Dirichlet.  trinode [Klin][2][Np1].
+struct Lvl1 {
+  int Kl, P, Np;
+  double invM;
+  const double* ops;   // Dr1 (Np x Np) | LIFT1 (Np x 2)
+  const double* geo;
+  const int* info;
+  const int* trinode;
+  const double* gamma;
+  const double* Cji;   // P x P
+  const double* Cij;
+  const double* G;     // 2P x 2P
+  const double* H;
+};
+
+// 0D level (corners).  info [Kpnt][3][2]: line, end; nrm [Kpnt][3].
+struct Lvl0 {
+  int Kp, P;
+  const int* info;
+  const double* nrm;
+  const double* T;     // 3P^2 x 3P^2
+};
+
+hipError_t launch_level3(const Lvl3& L, const double* qo, double* qn, double* res,
+                         const double* qb3, double A, double B, double dt, int src_e,
+                         const double* src_w, double src_s, hipStream_t st);
+hipError_t launch_level2(const Lvl2& L, const Lvl3& L3, const double* q2o, double* q2n,
+                         double* res2, const double* qb2, double* qb3, double* q03,
+                         const double* q3n, double A, double B, double dt, hipStream_t st);
+hipError_t launch_level1(const Lvl1& L, const Lvl2& L2, const double* q1o, double* q1n,
+                         double* res1, const double* qb1, double* qb2, double* q02,
+                         const double* q2n, double A, double B, double dt, hipStream_t st);
+hipError_t launch_level0(const Lvl0& L, const Lvl1& L1, const double* q1n, double* qb1,
+                         hipStream_t st);
+// FP64 energy partial sums: one value per tile written to out[ntile].
+hipError_t launch_energy(const Lvl3& L, const double* q, const double* mass, const double* J,
+                         double* out, hipStream_t st);
+
+}  // namespace dgh

@@ -1,0 +1,75 @@
+"""CPU tests of the C ABI: the library loads and exports every declared
+symbol; the host-side setup (no GPU calls) agrees with the oracle on counts
+and node coordinates; argument and call-order errors are reported."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as w
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1610_05023_amd", "libdghabc.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "dghabc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dgh_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    import ctypes
+    lib = ctypes.CDLL(LIB)
+    names = declared_symbols()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("n,N,P,bc", [(3, 2, 2, ("habc",) * 6), (4, 3, 3, ("habc",) * 6),
+                                      (3, 4, 6, ("habc", "habc", "dirichlet", "habc", "abc", "habc"))])
+def test_host_setup_matches_oracle(n, N, P, bc):
+    from oracle.solver import Oracle
+    from paper_1610_05023_amd import Solver
+    VX, E = w.kuhn_mesh(n)
+    K = E.shape[0]
+    o = Oracle(VX, E, N, P, np.ones(K), np.ones(K), face_bc=bc)
+    s = Solver(VX, E, N, P, np.ones(K), np.ones(K), face_bc=bc)
+    k = s.counts
+    assert (k["K"], k["Ktri"], k["Klin"], k["Kpnt"]) == (o.m.K, o.m.Ktri, o.m.Klin, o.m.Kpnt)
+    assert s.shapes() == o.shapes()
+    assert np.abs(s.node_coords() - o.node_coords()).max() < 1e-14
+
+
+def test_kuhn_counts():
+    from paper_1610_05023_amd import Solver
+    n = 5
+    VX, E = w.kuhn_mesh(n)
+    s = Solver(VX, E, 2, 2, np.ones(E.shape[0]), np.ones(E.shape[0]))
+    k = s.counts
+    assert (k["Ktri"], k["Klin"], k["Kpnt"]) == (12 * n * n, 12 * n, 8)
+
+
+def test_errors_reported():
+    from paper_1610_05023_amd import Solver, DghError
+    VX, E = w.kuhn_mesh(2)
+    K = E.shape[0]
+    with pytest.raises(DghError, match="EINVAL"):
+        Solver(VX, E, 9, 1, np.ones(K), np.ones(K))          # degree out of range
+    with pytest.raises(DghError, match="EINVAL"):
+        Solver(VX, E, 2, 13, np.ones(K), np.ones(K))         # HABC order out of range
+    with pytest.raises(DghError, match="EINVAL"):
+        Solver(VX, E, 2, 1, -np.ones(K), np.ones(K))         # negative density
+    bad = E.copy()
+    bad[0, [2, 3]] = bad[0, [3, 2]]                           # inverted tet
+    with pytest.raises(DghError, match="EINVAL"):
+        Solver(VX, bad, 2, 1, np.ones(K), np.ones(K))
+    s = Solver(VX, E, 2, 1, np.ones(K), np.ones(K))
+    with pytest.raises(DghError, match="ESTATE"):
+        s.step(1, 1e-3)                                       # before bind
+    with pytest.raises(DghError, match="ENOMEM"):
+        s._call("dgh_bind_workspace", None, 16, None)         # workspace too small

@@ -1,0 +1,112 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle: every
+state array of every level, relative l2 <= 1e-12 (the FP64 target; both
+sides compute the same deterministic linear map, so the difference is
+round-off of reordered sums and fused multiply-adds)."""
+import numpy as np
+import pytest
+
+import workloads as w
+from parity_util import make_case, make_solver, run_oracle, rel_errors
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _check(case, steps, dt, t0=0.0, tol=TOL):
+    print(f"[parity] N={case['N']} P={case['P']} K={case['E'].shape[0]} steps={steps}", flush=True)
+    s = make_solver(case)
+    s.step(steps, dt, t0)
+    got = s.read_fields()
+    ref = run_oracle(case, steps, dt, t0)
+    err = rel_errors(got, ref)
+    print("[parity] errors", {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
+    bad = {k: v for k, v in err.items() if not v <= tol}
+    assert not bad, bad
+    return s, got, ref
+
+
+def test_periodic_plane_wave():
+    n, N = 4, 3
+    case = make_case(n=n, N=N, P=0, face_bc=("periodic",) * 6, periodic=(True,) * 3, init="zero")
+    x = case["oracle"].node_coords()
+    k = 2 * np.pi * np.array([1.0, 2.0, 1.0])
+    p = np.cos(x @ k)
+    kh = k / np.linalg.norm(k)
+    case["state"]["q3"] = np.stack([p, kh[0] * p, kh[1] * p, kh[2] * p], axis=1)
+    _check(case, 20, w.kuhn_dt(n, N, 1.0))
+
+
+def test_basic_abc_random():
+    case = make_case(n=4, N=3, P=0, face_bc=("abc",) * 6, init="random", seed=3)
+    _check(case, 20, 1e-3)
+
+
+def test_dirichlet_random():
+    case = make_case(n=3, N=2, P=0, face_bc=("dirichlet",) * 6, init="random", seed=4)
+    _check(case, 20, 1e-3)
+
+
+def test_config1_gaussian_100_steps():
+    """8^3 x 6 tets, N = 3, P = 3 on all faces, centred Gaussian (width
+    0.05), 100 steps at CFL 0.5."""
+    cfg = w.config("1")
+    case = make_case(n=cfg.n, N=cfg.N, P=cfg.P, width=0.05)
+    _check(case, cfg.steps, cfg.dt)
+
+
+def test_config1c_random_all_levels():
+    """Config-1 mesh with every state array of every level random (seed 11):
+    all four levels and their couplings are exercised from the first stage."""
+    cfg = w.config("1c")
+    case = make_case(n=cfg.n, N=cfg.N, P=cfg.P, init="random", seed=11)
+    _check(case, cfg.steps, cfg.dt)
+
+
+def test_wave_through_faces_edges_corners():
+    """n = 4, N = 3, P = 3, a wide pulse run to t = 1.38: the wave crosses
+    the faces (t = 0.5), the edges (0.71) and the corners (0.87)."""
+    n, N = 4, 3
+    dt = w.kuhn_dt(n, N, 1.0)
+    case = make_case(n=n, N=N, P=3, width=0.15)
+    _, got, ref = _check(case, 500, dt)
+    assert np.abs(ref["qb1"]).max() > 1e-8
+
+
+def test_layered_medium_with_source():
+    """Five random layers (seed 2) on 8^3 x 6 tets, N = 3, P = 3, Ricker
+    source off the centre: heterogeneous upwind fluxes and the source term."""
+    n, N = 8, 3
+    h = 1.0 / n
+    xs = (0.5 + 0.3 * h, 0.5 + 0.2 * h, 0.5 + 0.1 * h)
+    case = make_case(n=n, N=N, P=3, medium="layered", init="zero", source=(xs, 6.0, 0.15))
+    _check(case, 60, w.kuhn_dt(n, N, 3.0))
+
+
+def test_order6_degree4_random():
+    case = make_case(n=3, N=4, P=6, init="random", seed=21)
+    _check(case, 20, 5e-4)
+
+
+def test_mixed_faces_random():
+    """Free surface (p = 0) on z+, basic ABC on y-, HABC elsewhere."""
+    case = make_case(n=3, N=3, P=2, face_bc=("habc", "habc", "abc", "habc", "habc", "dirichlet"),
+                     init="random", seed=31)
+    _check(case, 20, 1e-3)
+
+
+def test_energy_matches_oracle():
+    case = make_case(n=4, N=3, P=3, init="random", seed=41)
+    s = make_solver(case)
+    case["oracle"].s = {k: v.copy() for k, v in case["state"].items()}
+    assert abs(s.energy() - case["oracle"].energy()) <= 1e-12 * abs(case["oracle"].energy())
+
+
+def test_deterministic_rerun():
+    case = make_case(n=4, N=3, P=3, init="random", seed=51)
+    out = []
+    for _ in range(2):
+        s = make_solver(case)
+        s.step(10, 1e-3)
+        out.append(s.read_fields())
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
