@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Throughput of the FP64 DG + HABC time step on one MI355X.
+
+Workload: a 40^3 x 6 = 384,000-tet Kuhn mesh of the unit cube, degree N = 4
+(Np = 35), HABC order P = 6 on all six faces with edge and corner
+compatibility, five random horizontal layers (seed 2), a Ricker point source
+near the centre.  A step is five Runge-Kutta stages, each running the volume,
+face, edge and corner levels (all of the step); inputs are resident in HBM
+before the timed region.
+
+Prints one JSON line: DOF-updates/s per RK stage (the paper's unknown count
+over all levels), the roofline of the dominant (3D) kernel from HIP events
+recorded by the library around each of its launches in the timed region,
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, nominal
+METRIC = "DOF-updates/s per RK stage (FP64 vs mixed/batched) + fraction of HBM roofline"
+
+
+def bytes_per_tet_stage(Np):
+    """Algorithmic HBM bytes of the 3D level per tet per stage: q and res read
+    and written (16 Np words of 8 bytes), 27 per-tet constants, 20 bytes of
+    connectivity."""
+    return 16 * Np * 8 + 27 * 8 + 20
+
+
+def build_workload(n=40, N=4, P=6):
+    import numpy as np
+    import workloads as w
+    cfg = w.config("2")
+    VX, E = w.kuhn_mesh(n)
+    rho, c, *_ = w.layered_medium(n, seed=2)
+    h = 1.0 / n
+    xs = (0.5 + 0.3 * h, 0.5 + 0.2 * h, 0.5 + 0.1 * h)
+    f0 = float(w.source_material(n, xs, c)) / (10.0 * h)
+    dt = w.kuhn_dt(n, N, float(c.max()))
+    return dict(VX=VX, E=E, rho=rho, c=c, xs=xs, f0=f0, t0=1.25 / f0, dt=dt, n=n, N=N, P=P,
+                cfg=cfg)
+
+
+def cpu_baseline(seconds_target=20.0):
+    """The FP64 oracle (numpy, as is) on a bounded sample of the workload:
+    the same medium recipe, degree and HABC order on a 20^3 x 6 = 48,000-tet
+    mesh, stepped for 2 steps (10 RK stages).  Per-element work is the same
+    as on the 40^3 mesh, so DOF-updates/s per stage carries over."""
+    import numpy as np
+    import workloads as w
+    from oracle.solver import Oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    n, N, P, steps = 20, 4, 6, 2
+    VX, E = w.kuhn_mesh(n)
+    rho, c, *_ = w.layered_medium(n, seed=2)
+    o = Oracle(VX, E, N, P, rho, c)
+    h = 1.0 / n
+    xs = (0.5 + 0.3 * h, 0.5 + 0.2 * h, 0.5 + 0.1 * h)
+    f0 = float(w.source_material(n, xs, c)) / (10.0 * h)
+    o.set_source(xs, f0, 1.25 / f0)
+    o.s["q3"] = w.random_array(o.s["q3"].shape, 1) * 1e-3
+    dt = w.kuhn_dt(n, N, float(c.max()))
+    t = time.perf_counter()
+    o.step(steps, dt)
+    el = time.perf_counter() - t
+    U = w.n_unknowns(o.m.K, o.m.Ktri, o.m.Klin, N, P)
+    return {"value": U * 5 * steps / el, "unit": "DOF-updates/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"numpy FP64 oracle, {o.m.K}-tet (20^3 x 6) mesh, N={N}, P={P}, same "
+                      f"layered medium and source recipe, {steps} steps ({5 * steps} RK stages) "
+                      f"in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n", type=int, default=40)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 1 GiB device copy first (reference for PMC byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md but not run.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads as w
+    from paper_1610_05023_amd import Solver
+
+    if args.calib_copy:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 3 x 1 GiB read + 1 GiB write", file=sys.stderr)
+        del x, y
+    wl = build_workload(n=args.n)
+    K = wl["E"].shape[0]
+    t_setup = time.perf_counter()
+    s = Solver(wl["VX"], wl["E"], wl["N"], wl["P"], wl["rho"], wl["c"], device=0).bind()
+    s.set_source(wl["xs"], wl["f0"], wl["t0"])
+    k = s.counts
+    U = w.n_unknowns(k["K"], k["Ktri"], k["Klin"], wl["N"], wl["P"])
+    print(f"[bench] setup {time.perf_counter() - t_setup:.1f} s; K={K} Ktri={k['Ktri']} "
+          f"Klin={k['Klin']} unknowns={U}", file=sys.stderr, flush=True)
+    dt = wl["dt"]
+    s.step(args.warmup, dt, 0.0)
+    torch.cuda.synchronize()
+    s.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps, dt, args.warmup * dt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms3, n3 = s.kernel_time(3)
+    s.kernel_timing(False)
+    fields = s.read_fields(["q3"])
+    finite = bool(np.all(np.isfinite(fields["q3"])))
+    value = U * 5 * args.steps / el
+    avg3_ms = ms3 / max(n3, 1)
+    alg = bytes_per_tet_stage(k["Np"]) * K
+    achieved = alg / (avg3_ms * 1e-3) / 1e9
+    print(f"[bench] {args.steps} steps in {el:.3f} s; 3D kernel avg {avg3_ms * 1e3:.1f} us over "
+          f"{n3} launches; finite={finite}", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = cpu_baseline()
+        except Exception as ex:  # reported, never fatal for the GPU figure
+            cpu = {"value": None, "error": repr(ex)}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"FP64 DG+HABC step, {args.n}^3 x 6 = {K}-tet Kuhn mesh of the "
+                               f"unit cube, N=4 (Np=35), HABC P=6 with edges and corners, 5 "
+                               f"random layers (seed 2), Ricker point source",
+                   "K_tet": K, "K_tri": k["Ktri"], "K_lin": k["Klin"], "K_pnt": k["Kpnt"],
+                   "N": wl["N"], "P": wl["P"], "unknowns": U, "dt": dt,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_level3 (3D volume + surface + LSRK update)",
+                     "avg_us": avg3_ms * 1e3, "alg_bytes_per_launch": alg},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -13,6 +13,7 @@
 #include "habc.hpp"
 #include "levels.hpp"
 #include "mesh.hpp"
+#include "order.hpp"
 
 namespace {
 
@@ -36,7 +37,7 @@ struct Layout {
   Region q3[2], res3, geo3, zn3, nbr3, ops3, fmask3, fmap3, mass3, J3, esum;
   Region q2[2], res2, qb3, q03, geo2, info2, tetnode2, nbrnode2, ops2, fmask2, gamma;
   Region q1[2], res1, qb2, q02, geo1, info1, trinode1, ops1, cji, cij, G, H;
-  Region qb1, info0, nrm0, T, srcw;
+  Region qb1, info0, nrm0, T, srcw, wtris, wlines, wcorners;
   Region* add(Region& r, size_t bytes) {
     r.off = total;
     r.bytes = bytes;
@@ -62,6 +63,8 @@ struct dgh_ctx {
   hipStream_t stream = nullptr;
   int cur = 0;
   int ntile = 0;
+  std::vector<int> slot2elem, elem2slot;  // element order of the 3D layout
+  bool structured = false;
   // source
   int src_elem = -1;
   double f0 = 0, t0 = 0, amp = 0;
@@ -74,6 +77,8 @@ struct dgh_ctx {
   dgh::Lvl2 L2{};
   dgh::Lvl1 L1{};
   dgh::Lvl0 L0{};
+  dgh::LvlB LB{};
+  std::vector<int> wtris, wlines, wcorners;  // boundary work list (host copy)
 };
 
 namespace {
@@ -111,9 +116,91 @@ struct HostArrays {
   bool map_ok = true;
 };
 
+// Groups lines that must be updated by one block: the three lines of a
+// corner, and lines sharing a triangle; each group also takes the triangles
+// next to its lines.  The remaining triangles are dealt in chunks of TPB.
+void build_worklist(dgh_ctx* c) {
+  const dgh::Mesh& m = c->mesh;
+  const int P = c->P, Pe = P > 0 ? P : 1;
+  const int NS = std::max(m.tri.Np, 3 * m.tri.Nfp);
+  const int TPB = std::max(1, 512 / (Pe * NS));
+  const int Kl = m.Klin, Kt = m.Ktri;
+  std::vector<int> parent(Kl);
+  for (int l = 0; l < Kl; ++l) parent[l] = l;
+  auto find = [&](int x) {
+    while (parent[x] != x) x = parent[x] = parent[parent[x]];
+    return x;
+  };
+  auto unite = [&](int a, int b) { parent[find(a)] = find(b); };
+  for (int p = 0; p < m.Kpnt; ++p) {
+    unite(m.pnt_line[3 * p], m.pnt_line[3 * p + 1]);
+    unite(m.pnt_line[3 * p], m.pnt_line[3 * p + 2]);
+  }
+  std::vector<int> tri_line(Kt, -1);
+  for (int l = 0; l < Kl; ++l)
+    for (int side = 0; side < 2; ++side) {
+      const int t = m.lin_tri[2 * l + side];
+      if (tri_line[t] >= 0) unite(tri_line[t], l);
+      tri_line[t] = l;
+    }
+  std::vector<std::vector<int>> glines, gtris, gcors;
+  std::vector<int> gid(Kl, -1);
+  for (int l = 0; l < Kl; ++l) {
+    const int r = find(l);
+    if (gid[r] < 0) {
+      gid[r] = (int)glines.size();
+      glines.emplace_back();
+      gtris.emplace_back();
+      gcors.emplace_back();
+    }
+    glines[gid[r]].push_back(l);
+  }
+  std::vector<char> tri_taken(Kt, 0);
+  for (size_t g = 0; g < glines.size(); ++g)
+    for (int l : glines[g])
+      for (int side = 0; side < 2; ++side) {
+        const int t = m.lin_tri[2 * l + side];
+        if (!tri_taken[t]) {
+          tri_taken[t] = 1;
+          gtris[g].push_back(t);
+        }
+      }
+  for (int p = 0; p < m.Kpnt; ++p) gcors[gid[find(m.pnt_line[3 * p])]].push_back(p);
+  int maxtri = TPB, maxlin = 0, maxcor = 0;
+  for (size_t g = 0; g < glines.size(); ++g) {
+    maxtri = std::max(maxtri, (int)gtris[g].size());
+    maxlin = std::max(maxlin, (int)glines[g].size());
+    maxcor = std::max(maxcor, (int)gcors[g].size());
+  }
+  std::vector<int> rest;
+  for (int t = 0; t < Kt; ++t)
+    if (!tri_taken[t]) rest.push_back(t);
+  const int nface = ((int)rest.size() + TPB - 1) / TPB;
+  const int nb = (int)glines.size() + nface;
+  const int ml = std::max(1, maxlin), mc = std::max(1, maxcor);
+  c->wtris.assign((size_t)nb * maxtri, -1);
+  c->wlines.assign((size_t)nb * ml, -1);
+  c->wcorners.assign((size_t)nb * mc, -1);
+  for (size_t g = 0; g < glines.size(); ++g) {
+    for (size_t k = 0; k < gtris[g].size(); ++k) c->wtris[g * maxtri + k] = gtris[g][k];
+    for (size_t k = 0; k < glines[g].size(); ++k) c->wlines[g * ml + k] = glines[g][k];
+    for (size_t k = 0; k < gcors[g].size(); ++k) c->wcorners[g * mc + k] = gcors[g][k];
+  }
+  for (int f = 0; f < nface; ++f)
+    for (int k = 0; k < TPB && f * TPB + k < (int)rest.size(); ++k)
+      c->wtris[((size_t)glines.size() + f) * maxtri + k] = rest[f * TPB + k];
+  dgh::LvlB& W = c->LB;
+  W.nblocks = Kt > 0 ? nb : 0;
+  W.TPB = TPB;
+  W.NS = NS;
+  W.maxtri = maxtri;
+  W.maxlin = maxlin;
+  W.maxcor = maxcor;
+}
+
 void build_host_arrays(dgh_ctx* c, HostArrays& h) {
   const dgh::Mesh& m = c->mesh;
-  const int K = m.K, Np = m.tet.Np, Nfp = m.tet.Nfp, nt = c->ntile;
+  const int Np = m.tet.Np, Nfp = m.tet.Nfp, nt = c->ntile;
   const int T = dgh::kTile;
   // ---- 3D
   h.geo3.assign((size_t)nt * 12 * T, 0.0);
@@ -123,12 +210,13 @@ void build_host_arrays(dgh_ctx* c, HostArrays& h) {
   for (int slot = 0; slot < nt * T; ++slot) {
     const int tile = slot / T, es = slot % T;
     double* g = &h.geo3[(size_t)tile * 12 * T + es];
-    if (slot >= K) {  // benign padding geometry, never written back
+    const int e = c->slot2elem[slot];
+    if (e < 0) {  // padding slot: benign geometry, 1/rho = 0 marks it, never written
       g[0] = g[4 * T] = g[8 * T] = 1.0;
-      g[9 * T] = g[10 * T] = g[11 * T] = 1.0;
+      g[9 * T] = 0.0;
+      g[10 * T] = g[11 * T] = 1.0;
       continue;
     }
-    const int e = slot;
     for (int k = 0; k < 9; ++k) g[k * T] = m.geo[9 * e + k];
     g[9 * T] = 1.0 / c->rho[e];
     g[10 * T] = c->rho[e] * c->c[e] * c->c[e];
@@ -138,7 +226,7 @@ void build_host_arrays(dgh_ctx* c, HostArrays& h) {
       const size_t o = ((size_t)tile * 4 + f) * T + es;
       const int e2 = m.EToE[4 * e + f];
       if (e2 >= 0) {
-        h.nbr3[o] = (e2 << 5) | (m.EToF[4 * e + f] << 3) | m.perm[4 * e + f];
+        h.nbr3[o] = (c->elem2slot[e2] << 5) | (m.EToF[4 * e + f] << 3) | m.perm[4 * e + f];
         h.zn3[o] = c->rho[e2] * c->c[e2];
       } else {
         const int df = m.bface[4 * e + f];
@@ -170,11 +258,30 @@ void build_host_arrays(dgh_ctx* c, HostArrays& h) {
       }
     }
   }
-  h.ops3.clear();
-  h.ops3.insert(h.ops3.end(), m.tet.Dr.begin(), m.tet.Dr.end());
-  h.ops3.insert(h.ops3.end(), m.tet.Ds.begin(), m.tet.Ds.end());
-  h.ops3.insert(h.ops3.end(), m.tet.Dt.begin(), m.tet.Dt.end());
-  h.ops3.insert(h.ops3.end(), m.tet.LIFT.begin(), m.tet.LIFT.end());
+  {
+    // MFMA A-fragments (see Lvl3::ops)
+    const int RG = (Np + 3) / 4, FK = (Nfp + 3) / 4;
+    h.ops3.assign(dgh::frag3_size(m.N), 0.0);
+    const dgh::Mat* Ds[3] = {&m.tet.Dr, &m.tet.Ds, &m.tet.Dt};
+    for (int d = 0; d < 3; ++d)
+      for (int rg = 0; rg < RG; ++rg)
+        for (int ks = 0; ks < RG; ++ks)
+          for (int t = 0; t < 16; ++t) {
+            const int row = 4 * rg + (t & 3), col = 4 * ks + (t >> 2);
+            if (row < Np && col < Np)
+              h.ops3[(((size_t)d * RG + rg) * RG + ks) * 16 + t] = (*Ds[d])[row * Np + col];
+          }
+    const size_t off = (size_t)3 * RG * RG * 16;
+    for (int rg = 0; rg < RG; ++rg)
+      for (int f = 0; f < 4; ++f)
+        for (int jj = 0; jj < FK; ++jj)
+          for (int t = 0; t < 16; ++t) {
+            const int row = 4 * rg + (t & 3), k = 4 * jj + (t >> 2);
+            if (row < Np && k < Nfp)
+              h.ops3[off + (((size_t)rg * 4 + f) * FK + jj) * 16 + t] =
+                  m.tet.LIFT[row * 4 * Nfp + f * Nfp + k];
+          }
+  }
   h.mass3 = m.tet.Mass;
   h.fmask3 = m.tet.Fmask;
   h.fmap3 = m.fmap;
@@ -191,7 +298,7 @@ void build_host_arrays(dgh_ctx* c, HostArrays& h) {
     h.geo2[t * 8 + 4] = 1.0 / c->rho[e];
     h.geo2[t * 8 + 5] = c->rho[e] * c->c[e] * c->c[e];
     h.geo2[t * 8 + 6] = c->rho[e] * c->c[e];
-    h.info2[t * 8 + 0] = e;
+    h.info2[t * 8 + 0] = c->elem2slot[e];
     h.info2[t * 8 + 1] = m.tri_dface[t] / 2;
     h.info2[t * 8 + 2] = (m.tri_dface[t] % 2) ? 1 : -1;
     for (int f = 0; f < 3; ++f) {
@@ -260,6 +367,8 @@ void build_host_arrays(dgh_ctx* c, HostArrays& h) {
   h.ops1 = m.line.Dr;
   h.ops1.insert(h.ops1.end(), m.line.LIFT.begin(), m.line.LIFT.end());
   (void)Np1;
+  // ---- work list of the boundary kernel
+  build_worklist(c);
   // ---- 0D
   h.info0.assign((size_t)m.Kpnt * 6, 0);
   h.nrm0 = m.pnt_nrm;
@@ -283,7 +392,7 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.geo3, (size_t)nt * 12 * T * d);
   L.add(L.zn3, (size_t)nt * 4 * T * d);
   L.add(L.nbr3, (size_t)nt * 4 * T * i4);
-  L.add(L.ops3, (size_t)(3 * Np * Np + Np * 4 * Nfp) * d);
+  L.add(L.ops3, (size_t)dgh::frag3_size(m.N) * d);
   L.add(L.fmask3, (size_t)4 * Nfp * i4);
   L.add(L.fmap3, (size_t)96 * Nfp * i4);
   L.add(L.mass3, (size_t)Np * Np * d);
@@ -323,6 +432,10 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.nrm0, (size_t)std::max(1, m.Kpnt * 3) * d);
   L.add(L.T, (size_t)std::max(1, 9 * P * P * P * P) * d);
   L.add(L.srcw, (size_t)Np * d);
+  build_worklist(c);
+  L.add(L.wtris, std::max<size_t>(1, c->wtris.size()) * i4);
+  L.add(L.wlines, std::max<size_t>(1, c->wlines.size()) * i4);
+  L.add(L.wcorners, std::max<size_t>(1, c->wcorners.size()) * i4);
 }
 
 template <class V>
@@ -380,25 +493,35 @@ void fill_levels(dgh_ctx* c) {
   z.P = c->P;
   z.info = dptr<int>(c, L.info0);
   z.nrm = dptr<double>(c, L.nrm0);
-  z.T = dptr<double>(c, L.T);
+  z.Tt = dptr<double>(c, L.T);
+  c->LB.tris = dptr<int>(c, L.wtris);
+  c->LB.lines = dptr<int>(c, L.wlines);
+  c->LB.corners = dptr<int>(c, L.wcorners);
 }
 
-// canonical [K][4][Np] <-> device [tile][4][Np][16]
-void to_tiles(const double* src, double* dst, int K, int Np, int ntile) {
+// canonical [K][4][Np] <-> device [tile][4][Np][16] in slot order
+void to_tiles(const double* src, double* dst, const std::vector<int>& slot2elem, int Np) {
   const int T = dgh::kTile;
-  std::fill(dst, dst + (size_t)ntile * 4 * Np * T, 0.0);
-  for (int e = 0; e < K; ++e)
+  const size_t nslot = slot2elem.size();
+  std::fill(dst, dst + nslot * 4 * Np, 0.0);
+  for (size_t slot = 0; slot < nslot; ++slot) {
+    const int e = slot2elem[slot];
+    if (e < 0) continue;
     for (int f = 0; f < 4; ++f)
       for (int n = 0; n < Np; ++n)
-        dst[(((size_t)(e / T) * 4 + f) * Np + n) * T + (e % T)] = src[((size_t)e * 4 + f) * Np + n];
+        dst[(((slot / T) * 4 + f) * Np + n) * T + (slot % T)] = src[((size_t)e * 4 + f) * Np + n];
+  }
 }
 
-void from_tiles(const double* src, double* dst, int K, int Np) {
+void from_tiles(const double* src, double* dst, const std::vector<int>& slot2elem, int Np) {
   const int T = dgh::kTile;
-  for (int e = 0; e < K; ++e)
+  for (size_t slot = 0; slot < slot2elem.size(); ++slot) {
+    const int e = slot2elem[slot];
+    if (e < 0) continue;
     for (int f = 0; f < 4; ++f)
       for (int n = 0; n < Np; ++n)
-        dst[((size_t)e * 4 + f) * Np + n] = src[(((size_t)(e / T) * 4 + f) * Np + n) * T + (e % T)];
+        dst[((size_t)e * 4 + f) * Np + n] = src[(((slot / T) * 4 + f) * Np + n) * T + (slot % T)];
+  }
 }
 
 }  // namespace
@@ -469,7 +592,11 @@ dgh_status dgh_set_habc(dgh_ctx* c, int P, const double* gamma, const int* face_
   if (!r.empty()) return fail(c, DGH_EINVAL, r);
   if (!dgh::build_habc(P, gamma, c->habc)) return fail(c, DGH_EINVAL, "bad HABC coefficients");
   c->P = P;
-  c->ntile = (m.K + dgh::kTile - 1) / dgh::kTile;
+  dgh::element_order(m, c->slot2elem, &c->structured);
+  c->ntile = (int)(c->slot2elem.size() / dgh::kTile);
+  c->elem2slot.assign(m.K, -1);
+  for (size_t i = 0; i < c->slot2elem.size(); ++i)
+    if (c->slot2elem[i] >= 0) c->elem2slot[c->slot2elem[i]] = (int)i;
   c->stage = S_HABC;
   return DGH_OK;
 }
@@ -562,7 +689,16 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
   HIPCHECK(c, upload(c, L.H, c->habc.H));
   HIPCHECK(c, upload(c, L.info0, h.info0));
   HIPCHECK(c, upload(c, L.nrm0, h.nrm0));
-  HIPCHECK(c, upload(c, L.T, c->habc.T));
+  {
+    const int n3 = 3 * c->P * c->P;
+    std::vector<double> Tt((size_t)n3 * n3);
+    for (int r = 0; r < n3; ++r)
+      for (int k = 0; k < n3; ++k) Tt[(size_t)k * n3 + r] = c->habc.T[(size_t)r * n3 + k];
+    HIPCHECK(c, upload(c, L.T, Tt));
+  }
+  HIPCHECK(c, upload(c, L.wtris, c->wtris));
+  HIPCHECK(c, upload(c, L.wlines, c->wlines));
+  HIPCHECK(c, upload(c, L.wcorners, c->wcorners));
   fill_levels(c);
   c->cur = 0;
   c->src_elem = -1;
@@ -582,7 +718,7 @@ dgh_status dgh_set_state(dgh_ctx* c, int shot, const double* const* arr) {
   std::vector<double> zero((size_t)m.K * 4 * Np, 0.0);
   for (int which : {DGH_Q3, DGH_RES3}) {
     const double* src = (arr && arr[which]) ? arr[which] : zero.data();
-    to_tiles(src, buf.data(), m.K, Np, c->ntile);
+    to_tiles(src, buf.data(), c->slot2elem, Np);
     const Region& r = which == DGH_Q3 ? L.q3[cur] : L.res3;
     HIPCHECK(c, hipMemcpy(c->ws + r.off, buf.data(), r.bytes, hipMemcpyHostToDevice));
   }
@@ -625,7 +761,7 @@ dgh_status dgh_read_fields(dgh_ctx* c, int shot, double* const* arr) {
     if (!arr[which]) continue;
     const Region& r = which == DGH_Q3 ? L.q3[cur] : L.res3;
     HIPCHECK(c, hipMemcpy(buf.data(), c->ws + r.off, r.bytes, hipMemcpyDeviceToHost));
-    from_tiles(buf.data(), arr[which], m.K, Np);
+    from_tiles(buf.data(), arr[which], c->slot2elem, Np);
   }
   struct Item { int idx; const Region* r; size_t n; };
   const Item items[] = {
@@ -681,7 +817,7 @@ dgh_status dgh_set_source(dgh_ctx* c, int shot, const double* xs, double f0, dou
     w[a] /= m.J[best];
   }
   HIPCHECK(c, hipMemcpy(c->ws + c->lay.srcw.off, w.data(), Np * sizeof(double), hipMemcpyHostToDevice));
-  c->src_elem = best;
+  c->src_elem = c->elem2slot[best];
   c->f0 = f0;
   c->t0 = t0;
   c->amp = amp;
@@ -720,16 +856,13 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
         HIPCHECK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
       }
-      HIPCHECK(c, dgh::launch_level2(c->L2, c->L3, dptr<double>(c, L.q2[o]), dptr<double>(c, L.q2[n]),
-                                     dptr<double>(c, L.res2), dptr<double>(c, L.qb2),
-                                     dptr<double>(c, L.qb3), dptr<double>(c, L.q03),
-                                     dptr<double>(c, L.q3[n]), kA[s], kB[s], dt, c->stream));
-      HIPCHECK(c, dgh::launch_level1(c->L1, c->L2, dptr<double>(c, L.q1[o]), dptr<double>(c, L.q1[n]),
-                                     dptr<double>(c, L.res1), dptr<double>(c, L.qb1),
-                                     dptr<double>(c, L.qb2), dptr<double>(c, L.q02),
-                                     dptr<double>(c, L.q2[n]), kA[s], kB[s], dt, c->stream));
-      HIPCHECK(c, dgh::launch_level0(c->L0, c->L1, dptr<double>(c, L.q1[n]), dptr<double>(c, L.qb1),
-                                     c->stream));
+      HIPCHECK(c, dgh::launch_boundary(c->LB, c->L2, c->L1, c->L0, c->L3, dptr<double>(c, L.q2[o]),
+                                       dptr<double>(c, L.q2[n]), dptr<double>(c, L.res2),
+                                       dptr<double>(c, L.qb2), dptr<double>(c, L.qb3),
+                                       dptr<double>(c, L.q03), dptr<double>(c, L.q3[n]),
+                                       dptr<double>(c, L.q1[o]), dptr<double>(c, L.q1[n]),
+                                       dptr<double>(c, L.res1), dptr<double>(c, L.qb1),
+                                       dptr<double>(c, L.q02), kA[s], kB[s], dt, c->stream));
       c->cur = n;
     }
   }

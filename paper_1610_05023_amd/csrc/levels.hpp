@@ -8,6 +8,13 @@ namespace dgh {
 
 constexpr int kTile = 16;  // elements per tile of the 3D node-major layout
 
+// Number of doubles of the 3D operator fragments for degree N.
+inline int frag3_size(int N) {
+  const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
+  const int RG = (Np + 3) / 4, FK = (Nfp + 3) / 4;
+  return (3 * RG * RG + RG * 4 * FK) * 16;
+}
+
 // 3D level.  State layout [tile][field][node][16]; geometry [tile][12][16]:
 // rx ry rz sx sy sz tx ty tz 1/rho rho*c^2 rho*c; zn [tile][4][16] impedance
 // of the neighbour across each face; nbr [tile][4][16] face codes:
@@ -17,7 +24,11 @@ constexpr int kTile = 16;  // elements per tile of the 3D node-major layout
 //          2 = Dirichlet
 struct Lvl3 {
   int K, ntile, N, Np, Nfp;
-  const double* ops;   // Dr | Ds | Dt (Np x Np each) | LIFT (Np x 4Nfp), row-major
+  // A-fragments of the FP64 4x4x4 MFMA: Dr, Ds, Dt as [3][RG][RG][16] with
+  // entry t = i + 4 k holding D[4 rg + i][4 ks + k], then LIFT as
+  // [RG][4 faces][FK][16] with entry t holding LIFT[4 rg + i][f Nfp + 4 jj + k];
+  // zero outside the matrix.  RG = ceil(Np/4), FK = ceil(Nfp/4).
+  const double* ops;
   const int* fmask;    // 4 x Nfp
   const int* fmap;     // 4 x 4 x 6 x Nfp
   const double* geo;
@@ -68,20 +79,29 @@ struct Lvl0 {
   int Kp, P;
   const int* info;
   const double* nrm;
-  const double* T;     // 3P^2 x 3P^2
+  const double* Tt;    // transposed corner map: Tt[k][row] = T[row][k], 3P^2 x 3P^2
 };
 
 hipError_t launch_level3(const Lvl3& L, const double* qo, double* qn, double* res,
                          const double* qb3, double A, double B, double dt, int src_e,
                          const double* src_w, double src_s, hipStream_t st);
-hipError_t launch_level2(const Lvl2& L, const Lvl3& L3, const double* q2o, double* q2n,
-                         double* res2, const double* qb2, double* qb3, double* q03,
-                         const double* q3n, double A, double B, double dt, hipStream_t st);
-hipError_t launch_level1(const Lvl1& L, const Lvl2& L2, const double* q1o, double* q1n,
-                         double* res1, const double* qb1, double* qb2, double* q02,
-                         const double* q2n, double A, double B, double dt, hipStream_t st);
-hipError_t launch_level0(const Lvl0& L, const Lvl1& L1, const double* q1n, double* qb1,
-                         hipStream_t st);
+// Work list of the merged boundary kernel: block b updates the triangles
+// tris[b][*], then the lines lines[b][*] (each with its edge system), then
+// the corners corners[b][*]; -1 ends a list.  Blocks with lines hold every
+// triangle adjacent to their lines and every line of their corners.
+struct LvlB {
+  int nblocks, TPB, NS, maxtri, maxlin, maxcor;
+  const int* tris;
+  const int* lines;
+  const int* corners;
+};
+
+// 2D, 1D and 0D levels of one stage in one launch.
+hipError_t launch_boundary(const LvlB& W, const Lvl2& L2, const Lvl1& L1, const Lvl0& L0,
+                           const Lvl3& L3, const double* q2o, double* q2n, double* res2,
+                           double* qb2, double* qb3, double* q03, const double* q3n,
+                           const double* q1o, double* q1n, double* res1, double* qb1,
+                           double* q02, double A, double B, double dt, hipStream_t st);
 // FP64 energy partial sums: one value per tile written to out[ntile].
 hipError_t launch_energy(const Lvl3& L, const double* q, const double* mass, const double* J,
                          double* out, hipStream_t st);
