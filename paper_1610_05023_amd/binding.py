@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdghabc.so")
+# DGHABC_LIB may point at another build of the same library (e.g. a tuning
+# variant); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("DGHABC_LIB", os.path.join(_HERE, "libdghabc.so"))
 
 DGH_OK = 0
 STATUS = {0: "DGH_OK", -1: "DGH_EINVAL", -2: "DGH_ESTATE", -3: "DGH_EHIP", -4: "DGH_ENOMEM",

@@ -403,7 +403,7 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.q2[0], s2);
   L.add(L.q2[1], s2);
   L.add(L.res2, s2);
-  L.add(L.qb3, (size_t)std::max(1, Kt * Np2) * d);
+  L.add(L.qb3, (size_t)std::max(Nfp, Kt * Np2) * d);  // >= one triangle (read masked)
   L.add(L.q03, (size_t)std::max(1, Kt * Np2) * d);
   L.add(L.geo2, (size_t)std::max(1, Kt * 8) * d);
   L.add(L.info2, (size_t)std::max(1, Kt * 8) * i4);

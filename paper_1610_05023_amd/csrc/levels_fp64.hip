@@ -54,6 +54,9 @@ __device__ __forceinline__ void bcflux(int bc, double pM, double unM, double Z, 
 //   B (fields at nodes 4ks + k of the 16 elements):  lane l -> B[l/16][l%16]
 //   D (rows 4rg + k, elements):                       lane l -> D[l/16][l%16]
 // so each instruction accumulates one double per lane.
+// waves (tiles) per workgroup of the 3D kernel
+constexpr int kWaves3 = 4;
+
 template <int N>
 struct Dims3 {
   static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
@@ -77,7 +80,7 @@ __device__ __forceinline__ int xcd_block(int bid, int nblocks) {
 }
 
 template <int N>
-__global__ void __launch_bounds__(256, 2) k_level3(Lvl3 L, const double* __restrict__ qo,
+__global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double* __restrict__ qo,
                                                    double* __restrict__ qn, double* __restrict__ res,
                                                    const double* __restrict__ qb3, double A, double B,
                                                    double dt, int src_e,
@@ -96,7 +99,7 @@ __global__ void __launch_bounds__(256, 2) k_level3(Lvl3 L, const double* __restr
     for (int i = threadIdx.x; i < D::NFRAG * 16; i += blockDim.x) sops[i] = L.ops[i];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int tile = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  const int tile = xcd_block(blockIdx.x, gridDim.x) * kWaves3 + (threadIdx.x >> 6);
   if (tile >= L.ntile) return;
   const int es = lane & 15, g = lane >> 4;
   const int ta = (lane & 3) + 4 * g;   // this lane's entry of a 16-value A fragment
@@ -115,43 +118,60 @@ __global__ void __launch_bounds__(256, 2) k_level3(Lvl3 L, const double* __restr
   double dpr[RG], dps[RG], dpt[RG], dv[RG];
 #pragma unroll
   for (int i = 0; i < RG; ++i) dpr[i] = dps[i] = dpt[i] = dv[i] = 0.0;
-  double p = 0, u = 0, v = 0, w = 0;
-  if (g < Np) {
-    p = qt[(0 * Np + g) * kTile];
-    u = qt[(1 * Np + g) * kTile];
-    v = qt[(2 * Np + g) * kTile];
-    w = qt[(3 * Np + g) * kTile];
+  // fields of the lane's nodes 4 j + g, loaded PF k-steps ahead (fewer for
+  // N > 4, where the accumulators leave no registers for it)
+  constexpr int PF = N <= 4 ? 3 : 1;
+  double bp[PF], bu[PF], bv[PF], bw[PF];
+  // loads are issued unconditionally at clamped (in-range) nodes and masked
+  // afterwards, so that no load sits behind a divergent branch
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    const int node = 4 * k + g;
+    const bool in = k < RG && node < Np;
+    const int nc = min(node, Np - 1);
+    bp[k] = qt[(0 * Np + nc) * kTile];
+    bu[k] = qt[(1 * Np + nc) * kTile];
+    bv[k] = qt[(2 * Np + nc) * kTile];
+    bw[k] = qt[(3 * Np + nc) * kTile];
+    if (!in) bp[k] = bu[k] = bv[k] = bw[k] = 0.0;
   }
 #pragma unroll 1
-  for (int j = 0; j < RG; ++j) {
-    const int nn = 4 * (j + 1) + g;
-    double pn = 0, un = 0, vn = 0, wn = 0;
-    if (j + 1 < RG && nn < Np) {
-      pn = qt[(0 * Np + nn) * kTile];
-      un = qt[(1 * Np + nn) * kTile];
-      vn = qt[(2 * Np + nn) * kTile];
-      wn = qt[(3 * Np + nn) * kTile];
-    }
-    const double fr = rx * u + ry * v + rz * w;
-    const double fs = sx * u + sy * v + sz * w;
-    const double ft = tx * u + ty * v + tz * w;
-    const double* fj = frag + j * 16;
+  for (int j0 = 0; j0 < RG; j0 += PF) {
 #pragma unroll
-    for (int i = 0; i < RG; ++i) {
-      const double ar = fj[((0 * RG + i) * RG) * 16];
-      const double as = fj[((1 * RG + i) * RG) * 16];
-      const double at = fj[((2 * RG + i) * RG) * 16];
-      dpr[i] = mfma4(ar, p, dpr[i]);
-      dps[i] = mfma4(as, p, dps[i]);
-      dpt[i] = mfma4(at, p, dpt[i]);
-      dv[i] = mfma4(ar, fr, dv[i]);
-      dv[i] = mfma4(as, fs, dv[i]);
-      dv[i] = mfma4(at, ft, dv[i]);
+    for (int sl = 0; sl < PF; ++sl) {
+      const int j = j0 + sl;
+      if (j < RG) {
+        const double p = bp[sl], u = bu[sl], v = bv[sl], w = bw[sl];
+        {
+          const int jn = j + PF, node = 4 * jn + g;
+          const bool in = jn < RG && node < Np;
+          const int nc = min(node, Np - 1);
+          const double a0 = qt[(0 * Np + nc) * kTile], a1 = qt[(1 * Np + nc) * kTile];
+          const double a2 = qt[(2 * Np + nc) * kTile], a3 = qt[(3 * Np + nc) * kTile];
+          bp[sl] = in ? a0 : 0.0;
+          bu[sl] = in ? a1 : 0.0;
+          bv[sl] = in ? a2 : 0.0;
+          bw[sl] = in ? a3 : 0.0;
+        }
+        const double fr = rx * u + ry * v + rz * w;
+        const double fs = sx * u + sy * v + sz * w;
+        const double ft = tx * u + ty * v + tz * w;
+        const double* fj = frag + j * 16;
+#pragma unroll
+        for (int i = 0; i < RG; ++i) {
+          if (i % 3 == 0) __builtin_amdgcn_sched_barrier(0);
+          const double ar = fj[((0 * RG + i) * RG) * 16];
+          const double as = fj[((1 * RG + i) * RG) * 16];
+          const double at = fj[((2 * RG + i) * RG) * 16];
+          dpr[i] = mfma4(ar, p, dpr[i]);
+          dps[i] = mfma4(as, p, dps[i]);
+          dpt[i] = mfma4(at, p, dpt[i]);
+          dv[i] = mfma4(ar, fr, dv[i]);
+          dv[i] = mfma4(as, fs, dv[i]);
+          dv[i] = mfma4(at, ft, dv[i]);
+        }
+      }
     }
-    p = pn;
-    u = un;
-    v = vn;
-    w = wn;
   }
   // in place: dv -> rhs_p, (dpr, dps, dpt) -> rhs_(u, v, w)
 #pragma unroll
@@ -186,43 +206,50 @@ __global__ void __launch_bounds__(256, 2) k_level3(Lvl3 L, const double* __restr
     nz *= inv;
     const int code = nbrt[f * kTile];
     const double ZP = znt[f * kTile];
-    const double* q2 = qo;
-    int mapbase;
-    if (code >= 0) {
-      const int e2 = code >> 5;
-      q2 = qo + (size_t)(e2 >> 4) * 4 * Np * kTile + (e2 & 15);
-      mapbase = ((f * 4 + ((code >> 3) & 3)) * 6 + (code & 7)) * Nfp;
-    } else {
-      const int c = -1 - code;
-      mapbase = ((f * 4) * 6 + ((c >> 2) & 7)) * Nfp;
-    }
+    // interior faces gather from the neighbour; boundary faces read their own
+    // element there (ignored) and the HABC characteristic qb3 (triangle 0 for
+    // interior faces, ignored) -- every load is issued, then results selected
+    const bool inner = code >= 0;
+    const int cb = -1 - code;
+    const int bc = inner ? -1 : (cb & 3);
+    const int e2 = inner ? (code >> 5) : e;
+    const double* q2 = qo + (size_t)(e2 >> 4) * 4 * Np * kTile + (e2 & 15);
+    const int mapbase = inner ? ((f * 4 + ((code >> 3) & 3)) * 6 + (code & 7)) * Nfp
+                              : ((f * 4) * 6 + ((cb >> 2) & 7)) * Nfp;
+    const double* qbt = qb3 + (size_t)((!inner && bc == 0) ? (cb >> 5) : 0) * Nfp;
+    // upwind weights of this face (exact-Riemann flux, Section 3.2)
+    const double iZ = 1.0 / (Z + ZP);
+    const double iZb = 1.0 / Z;
     double tmp[RG];
 #pragma unroll
     for (int i = 0; i < RG; ++i) tmp[i] = 0.0;
 #pragma unroll
     for (int jj = 0; jj < FK; ++jj) {
       const int k = 4 * jj + g;
-      double fp = 0.0, fu = 0.0;
-      if (k < Nfp) {
-        const int n = smask[f * Nfp + k];
-        const int n2 = smap[mapbase + k];
-        const double pM = qt[n * kTile];
-        const double unM = nx * qt[(Np + n) * kTile] + ny * qt[(2 * Np + n) * kTile] +
-                           nz * qt[(3 * Np + n) * kTile];
-        double pF, unF;
-        if (code >= 0) {
-          const double pP = q2[n2 * kTile];
-          const double unP = nx * q2[(Np + n2) * kTile] + ny * q2[(2 * Np + n2) * kTile] +
-                             nz * q2[(3 * Np + n2) * kTile];
-          upwind(pM, unM, Z, pP, unP, ZP, pF, unF);
-        } else {
-          const int c = -1 - code, bc = c & 3;
-          const double rm = bc == 0 ? qb3[(size_t)(c >> 5) * Nfp + n2] : 0.0;
-          bcflux(bc, pM, unM, Z, rm, pF, unF);
-        }
-        fp = fsc * Kb * (unM - unF);
-        fu = fsc * irho * (pM - pF);
-      }
+      const int kc = min(k, Nfp - 1);
+      const int n = smask[f * Nfp + kc];
+      const int n2 = smap[mapbase + kc];
+      const double pM = qt[n * kTile];
+      const double uM = qt[(Np + n) * kTile], vM = qt[(2 * Np + n) * kTile],
+                   wM = qt[(3 * Np + n) * kTile];
+      const double pP = q2[n2 * kTile];
+      const double uP = q2[(Np + n2) * kTile], vP = q2[(2 * Np + n2) * kTile],
+                   wP = q2[(3 * Np + n2) * kTile];
+      const double rb = qbt[min(n2, Nfp - 1)];
+      const double unM = nx * uM + ny * vM + nz * wM;
+      const double unP = nx * uP + ny * vP + nz * wP;
+      // all three flux forms, then a select (no divergent branch)
+      const double pFi = (ZP * pM + Z * pP + Z * ZP * (unM - unP)) * iZ;   // upwind
+      const double unFi = (pM - pP + Z * unM + ZP * unP) * iZ;
+      const double rpl = 0.5 * (pM + Z * unM);                            // characteristic
+      const double rmi = bc == 0 ? rb : 0.0;
+      const double pFc = rpl + rmi, unFc = (rpl - rmi) * iZb;
+      const double unFd = unM + pM * iZb;                                // p = 0
+      const double pF = inner ? pFi : (bc == 2 ? 0.0 : pFc);
+      const double unF = inner ? unFi : (bc == 2 ? unFd : unFc);
+      const bool valid = k < Nfp;
+      const double fp = valid ? fsc * Kb * (unM - unF) : 0.0;
+      const double fu = valid ? fsc * irho * (pM - pF) : 0.0;
       const double* fl = fragL + (f * FK + jj) * 16;
 #pragma unroll
       for (int i = 0; i < RG; ++i) {
@@ -239,20 +266,43 @@ __global__ void __launch_bounds__(256, 2) k_level3(Lvl3 L, const double* __restr
     }
   }
 
-  // ---- LSRK update of the rows this lane holds (1/rho = 0 marks padding)
-  if (irho != 0.0) {
+  // ---- LSRK update of the rows this lane holds (1/rho = 0 marks padding),
+  // in chunks of row groups so that the loads in flight fit the registers;
+  // loads at clamped rows, stores masked
+  {
+    const bool live = irho != 0.0;
     const bool src = e == src_e;
+    constexpr int EC = 3;
 #pragma unroll
-    for (int i = 0; i < RG; ++i) {
-      const int n = 4 * i + g;
-      if (n < Np) {
-        const double rhs[4] = {rp[i] + (src ? src_w[n] * src_s : 0.0), ru[i], rv[i], rw[i]};
+    for (int i0 = 0; i0 < RG; i0 += EC) {
+      __builtin_amdgcn_sched_barrier(0);
+      double ro[EC][4], qo_[EC][4];
+#pragma unroll
+      for (int ii = 0; ii < EC; ++ii) {
+        const int nc = min(4 * (i0 + ii) + g, Np - 1);
 #pragma unroll
         for (int fl = 0; fl < 4; ++fl) {
-          const size_t idx = ((size_t)(tile * 4 + fl) * Np + n) * kTile + es;
-          const double rr = A * res[idx] + dt * rhs[fl];
-          res[idx] = rr;
-          qn[idx] = qt[(fl * Np + n) * kTile] + B * rr;
+          const size_t idx = ((size_t)(tile * 4 + fl) * Np + nc) * kTile + es;
+          ro[ii][fl] = (i0 + ii < RG) ? res[idx] : 0.0;
+          qo_[ii][fl] = (i0 + ii < RG) ? qt[(fl * Np + nc) * kTile] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int ii = 0; ii < EC; ++ii) {
+        const int i = i0 + ii;
+        if (i >= RG) continue;
+        const int n = 4 * i + g;
+        const int nc = min(n, Np - 1);
+        const double sw = src_w[nc];
+        const double rhs[4] = {rp[i] + (src ? sw * src_s : 0.0), ru[i], rv[i], rw[i]};
+        if (live && n < Np) {
+#pragma unroll
+          for (int fl = 0; fl < 4; ++fl) {
+            const size_t idx = ((size_t)(tile * 4 + fl) * Np + n) * kTile + es;
+            const double rr = A * ro[ii][fl] + dt * rhs[fl];
+            res[idx] = rr;
+            qn[idx] = qo_[ii][fl] + B * rr;
+          }
         }
       }
     }
@@ -306,8 +356,8 @@ hipError_t launch3(const Lvl3& L, const double* qo, double* qn, double* res, con
                         (int)lds);
     attr = true;
   }
-  const int blocks = (L.ntile + 3) / 4;
-  hipLaunchKernelGGL(k_level3<N>, dim3(blocks), dim3(256), lds, st, L, qo, qn, res, qb3, A, B,
+  const int blocks = (L.ntile + kWaves3 - 1) / kWaves3;
+  hipLaunchKernelGGL(k_level3<N>, dim3(blocks), dim3(kWaves3 * 64), lds, st, L, qo, qn, res, qb3, A, B,
                      dt, src_e, src_w, src_s);
   return hipGetLastError();
 }
