@@ -141,6 +141,16 @@ dgh_status dgh_step(dgh_ctx* ctx, int n_steps, double dt, double t_start);
  * of one shot (the energy weights of Section 4.1).  Synchronises. */
 dgh_status dgh_energy(dgh_ctx* ctx, int shot, double* e);
 
+/* Failure check (the energy of Section 4.1 as a stability monitor): scans
+ * every state array of every level of one shot for non-finite values and
+ * computes the FP64 energy (written to *e_out when e_out is not NULL).
+ * Returns DGH_ENONFINITE if any value (or the energy) is not finite, else
+ * DGH_EUNSTABLE if e_ref > 0 and the energy exceeds e_ref (1 + rel_tol)
+ * (rel_tol >= 0, else DGH_EINVAL), else DGH_OK.  The state is left as
+ * computed, so the caller may restore its own checkpoint with
+ * dgh_set_state.  Synchronises. */
+dgh_status dgh_check(dgh_ctx* ctx, int shot, double e_ref, double rel_tol, double* e_out);
+
 /* Per-kernel timing with HIP events on the bound stream: enable = 1 starts
  * recording around every 3D-level launch, 0 stops.  dgh_kernel_time returns
  * the accumulated milliseconds and launch count of level `level` (3, 2, 1,

@@ -41,6 +41,7 @@ _SIGS = {
     "dgh_set_source": [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_double, C.c_double],
     "dgh_step": [C.c_void_p, C.c_int, C.c_double, C.c_double],
     "dgh_energy": [C.c_void_p, C.c_int, C.POINTER(C.c_double)],
+    "dgh_check": [C.c_void_p, C.c_int, C.c_double, C.c_double, C.POINTER(C.c_double)],
     "dgh_kernel_timing": [C.c_void_p, C.c_int],
     "dgh_kernel_time": [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
     "dgh_last_error": [C.c_void_p],
@@ -195,6 +196,16 @@ class Solver:
         e = C.c_double()
         self._call("dgh_energy", shot, C.byref(e))
         return e.value
+
+    def check(self, e_ref=0.0, rel_tol=0.0, shot=0):
+        """Returns (status name, energy): DGH_OK, DGH_ENONFINITE or
+        DGH_EUNSTABLE; other failures raise."""
+        e = C.c_double()
+        st = self.lib.dgh_check(self.h, shot, float(e_ref), float(rel_tol), C.byref(e))
+        if st not in (DGH_OK, -5, -6):
+            msg = self.lib.dgh_last_error(self.h).decode()
+            raise DghError(f"dgh_check: {STATUS.get(st, st)}: {msg}")
+        return STATUS[st], e.value
 
     def kernel_timing(self, enable):
         self._call("dgh_kernel_timing", 1 if enable else 0)

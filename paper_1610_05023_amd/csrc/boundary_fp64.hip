@@ -70,8 +70,9 @@ __global__ void __launch_bounds__(512) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0
     for (int x = tid; x < 2 * Np * Np + Np * NE; x += nth) sDr[x] = L2.ops[x];
     const int per = Pe * NS;
     const int tl = tid / per, rem = tid - tl * per, i = rem / NS, slot = rem - i * NS;
-    for (int c0 = 0; c0 < W.maxtri; c0 += TPB) {
-      const int t = (tl < TPB && c0 + tl < W.maxtri) ? W.tris[blk * W.maxtri + c0 + tl] : -1;
+    const int ntri = W.ntri[blk];
+    for (int c0 = 0; c0 < ntri; c0 += TPB) {
+      const int t = (tl < TPB && c0 + tl < ntri) ? W.tris[blk * W.maxtri + c0 + tl] : -1;
       __syncthreads();
       if (t >= 0)
         for (int x = rem; x < P * 3 * Np; x += per)
@@ -82,6 +83,42 @@ __global__ void __launch_bounds__(512) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0
         const double* gg = L2.geo + (size_t)t * 8;
         rx = gg[0]; ry = gg[1]; sx = gg[2]; sy = gg[3]; irho = gg[4]; Kb = gg[5]; Z = gg[6];
         for (int k = 0; k < 6; ++k) info[k] = L2.info[t * 8 + k];
+      }
+      const bool act = t >= 0 && i < P;
+      // loads of this thread that do not depend on the tile: the previous
+      // residual and q0 of its node, the new 3D trace for the face rule, and
+      // the neighbour's trace (or the edge characteristic) of its edge node
+      double r0 = 0, r1 = 0, r2 = 0, S0 = 0, p3 = 0, u3 = 0;
+      if (act && slot < Np) {
+        const size_t base = ((size_t)t * P + i) * 3 * Np + slot;
+        r0 = b.res2[base];
+        r1 = b.res2[base + Np];
+        r2 = b.res2[base + 2 * Np];
+        S0 = b.q03[(size_t)t * Np + slot];
+      }
+      if (t >= 0 && i == 0 && slot < Np) {
+        const int e = info[0], n3 = L2.tetnode[(size_t)t * Np + slot];
+        const double* q3 = b.q3n + (size_t)(e >> 4) * 4 * L3.Np * kTile + (e & 15);
+        p3 = q3[n3 * kTile];
+        u3 = q3[((1 + info[1]) * L3.Np + n3) * kTile];
+      }
+      int ef = 0, ek = 0, code = 0, nn = 0;
+      double gP = 0, gA = 0, gB = 0, gZ = 1, grm = 0;
+      if (act && slot < NE) {
+        ef = slot / Nfp;
+        ek = slot - ef * Nfp;
+        code = info[3 + ef];
+        nn = L2.nbrnode[(t * 3 + ef) * Nfp + ek];
+        if (code >= 0) {
+          const double* q = b.q2o + ((size_t)code * P + i) * 3 * Np;
+          gP = q[nn];
+          gA = q[Np + nn];
+          gB = q[2 * Np + nn];
+          gZ = L2.geo[(size_t)code * 8 + 6];
+        } else {
+          const int c = -1 - code;
+          if ((c & 3) == 0) grm = b.qb2[(((size_t)(c >> 3) * 2 + ((c >> 2) & 1)) * P + i) * Nfp + nn];
+        }
       }
       __syncthreads();
       const double* sqt = sq + (tl * P + i) * 3 * Np;
@@ -96,30 +133,21 @@ __global__ void __launch_bounds__(512) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0
           en[f][1] = t >= 0 ? v[f][1] / m : 0.0;
         }
       }
-      const bool act = t >= 0 && i < P;
       const double Ki = act ? Kb / (1.0 + L2.gamma[i]) : 0.0;
       // ---- fluxes on the 3 edges
       if (act && slot < NE) {
-        const int f = slot / Nfp, k = slot - f * Nfp;
-        const int a = L2.fmask[f * Nfp + k];
-        const double na = en[f][0], nb = en[f][1];
+        const int a = L2.fmask[ef * Nfp + ek];
+        const double na = en[ef][0], nb = en[ef][1];
         const double pM = sqt[a];
         const double vnM = na * sqt[Np + a] + nb * sqt[2 * Np + a];
-        const int code = info[3 + f];
-        const int nn = L2.nbrnode[(t * 3 + f) * Nfp + k];
         double pF, vnF;
-        if (code >= 0) {
-          const double* q = b.q2o + ((size_t)code * P + i) * 3 * Np;
-          upwind2(pM, vnM, Z, q[nn], na * q[Np + nn] + nb * q[2 * Np + nn],
-                  L2.geo[(size_t)code * 8 + 6], pF, vnF);
-        } else {
-          const int c = -1 - code, bc = c & 3, side = (c >> 2) & 1, l = c >> 3;
-          const double rm = bc == 0 ? b.qb2[(((size_t)l * 2 + side) * P + i) * Nfp + nn] : 0.0;
-          bcflux2(bc, pM, vnM, Z, rm, pF, vnF);
-        }
+        if (code >= 0)
+          upwind2(pM, vnM, Z, gP, na * gA + nb * gB, gZ, pF, vnF);
+        else
+          bcflux2((-1 - code) & 3, pM, vnM, Z, grm, pF, vnF);
         double* sft = sf + (tl * P + i) * 2 * NE;
-        sft[slot] = en[f][2] * Ki * (vnM - vnF);
-        sft[NE + slot] = en[f][2] * irho * (pM - pF);
+        sft[slot] = en[ef][2] * Ki * (vnM - vnF);
+        sft[NE + slot] = en[ef][2] * irho * (pM - pF);
       }
       __syncthreads();
       // ---- volume, lift, update of set i
@@ -142,34 +170,27 @@ __global__ void __launch_bounds__(512) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0
             lp += l * sft[j];
             lv[f] += l * sft[NE + j];
           }
-        double rhs[3];
-        rhs[0] = -Ki * div + lp;
-        rhs[1] = -irho * (rx * pr_ + sx * ps_);
-        rhs[2] = -irho * (ry * pr_ + sy * ps_);
+        double rhs1 = -irho * (rx * pr_ + sx * ps_), rhs2 = -irho * (ry * pr_ + sy * ps_);
         for (int f = 0; f < 3; ++f) {
-          rhs[1] += en[f][0] * lv[f];
-          rhs[2] += en[f][1] * lv[f];
+          rhs1 += en[f][0] * lv[f];
+          rhs2 += en[f][1] * lv[f];
         }
         const size_t base = ((size_t)t * P + i) * 3 * Np + a;
-        const double S0 = b.q03[(size_t)t * Np + a];
-        double r = A * b.res2[base] + dt * rhs[0];
-        b.res2[base] = r;
-        sps[(tl * P + i) * Np + a] = sqt[a] - S0 + B * r;
-        for (int fl = 1; fl < 3; ++fl) {
-          r = A * b.res2[base + fl * Np] + dt * rhs[fl];
-          b.res2[base + fl * Np] = r;
-          b.q2n[base + fl * Np] = sqt[fl * Np + a] + B * r;
-        }
+        r0 = A * r0 + dt * (-Ki * div + lp);
+        r1 = A * r1 + dt * rhs1;
+        r2 = A * r2 + dt * rhs2;
+        b.res2[base] = r0;
+        b.res2[base + Np] = r1;
+        b.res2[base + 2 * Np] = r2;
+        sps[(tl * P + i) * Np + a] = sqt[a] - S0 + B * r0;
+        b.q2n[base + Np] = sqt[Np + a] + B * r1;
+        b.q2n[base + 2 * Np] = sqt[2 * Np + a] + B * r2;
       }
       __syncthreads();
       // ---- face rule: r+ from the new 3D trace, r- = (1/M) sum g_i p*_i
       if (t >= 0 && i == 0 && slot < Np) {
         const int a = slot;
-        const int e = info[0], ax = info[1];
-        const double sgn = (double)info[2];
-        const int n3 = L2.tetnode[(size_t)t * Np + a];
-        const double* q3 = b.q3n + (size_t)(e >> 4) * 4 * L3.Np * kTile + (e & 15);
-        const double rp = 0.5 * (q3[n3 * kTile] + Z * sgn * q3[((1 + ax) * L3.Np + n3) * kTile]);
+        const double rp = 0.5 * (p3 + Z * (double)info[2] * u3);
         double rm = 0.0;
         for (int s = 0; s < P; ++s) rm += L2.gamma[s] * sps[(tl * P + s) * Np + a];
         rm *= L2.invM;

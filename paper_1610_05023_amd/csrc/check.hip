@@ -1,0 +1,31 @@
+// Finiteness scan of the state arrays (the failure check that accompanies
+// the energy of Section 4.1): one flag per block and array, no atomics.
+#include <hip/hip_runtime.h>
+
+#include "levels.hpp"
+
+namespace dgh {
+
+namespace {
+
+__global__ void __launch_bounds__(256) k_nonfinite(ScanList s, int* __restrict__ flags) {
+  const int a = blockIdx.y;
+  const double* __restrict__ p = s.ptr[a];
+  const size_t n = s.n[a];
+  int bad = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(p[i]);
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) flags[a * gridDim.x + blockIdx.x] = bad;
+}
+
+}  // namespace
+
+hipError_t launch_nonfinite(const ScanList& s, int* flags, hipStream_t st) {
+  if (s.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nonfinite, dim3(kScanBlocks, s.count), dim3(256), 0, st, s, flags);
+  return hipGetLastError();
+}
+
+}  // namespace dgh

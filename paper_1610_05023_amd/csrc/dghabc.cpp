@@ -37,7 +37,7 @@ struct Layout {
   Region q3[2], res3, geo3, zn3, nbr3, ops3, fmask3, fmap3, mass3, J3, esum;
   Region q2[2], res2, qb3, q03, geo2, info2, tetnode2, nbrnode2, ops2, fmask2, gamma;
   Region q1[2], res1, qb2, q02, geo1, info1, trinode1, ops1, cji, cij, G, H;
-  Region qb1, info0, nrm0, T, srcw, wtris, wlines, wcorners;
+  Region qb1, info0, nrm0, T, srcw, wntri, wtris, wlines, wcorners, flags;
   Region* add(Region& r, size_t bytes) {
     r.off = total;
     r.bytes = bytes;
@@ -78,7 +78,7 @@ struct dgh_ctx {
   dgh::Lvl1 L1{};
   dgh::Lvl0 L0{};
   dgh::LvlB LB{};
-  std::vector<int> wtris, wlines, wcorners;  // boundary work list (host copy)
+  std::vector<int> wntri, wtris, wlines, wcorners;  // boundary work list (host copy)
 };
 
 namespace {
@@ -178,17 +178,21 @@ void build_worklist(dgh_ctx* c) {
   const int nface = ((int)rest.size() + TPB - 1) / TPB;
   const int nb = (int)glines.size() + nface;
   const int ml = std::max(1, maxlin), mc = std::max(1, maxcor);
+  c->wntri.assign((size_t)std::max(1, nb), 0);
   c->wtris.assign((size_t)nb * maxtri, -1);
   c->wlines.assign((size_t)nb * ml, -1);
   c->wcorners.assign((size_t)nb * mc, -1);
   for (size_t g = 0; g < glines.size(); ++g) {
     for (size_t k = 0; k < gtris[g].size(); ++k) c->wtris[g * maxtri + k] = gtris[g][k];
+    c->wntri[g] = (int)gtris[g].size();
     for (size_t k = 0; k < glines[g].size(); ++k) c->wlines[g * ml + k] = glines[g][k];
     for (size_t k = 0; k < gcors[g].size(); ++k) c->wcorners[g * mc + k] = gcors[g][k];
   }
   for (int f = 0; f < nface; ++f)
-    for (int k = 0; k < TPB && f * TPB + k < (int)rest.size(); ++k)
+    for (int k = 0; k < TPB && f * TPB + k < (int)rest.size(); ++k) {
       c->wtris[((size_t)glines.size() + f) * maxtri + k] = rest[f * TPB + k];
+      c->wntri[glines.size() + f] = k + 1;
+    }
   dgh::LvlB& W = c->LB;
   W.nblocks = Kt > 0 ? nb : 0;
   W.TPB = TPB;
@@ -433,9 +437,11 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.T, (size_t)std::max(1, 9 * P * P * P * P) * d);
   L.add(L.srcw, (size_t)Np * d);
   build_worklist(c);
+  L.add(L.wntri, std::max<size_t>(1, c->wntri.size()) * i4);
   L.add(L.wtris, std::max<size_t>(1, c->wtris.size()) * i4);
   L.add(L.wlines, std::max<size_t>(1, c->wlines.size()) * i4);
   L.add(L.wcorners, std::max<size_t>(1, c->wcorners.size()) * i4);
+  L.add(L.flags, (size_t)dgh::kScanMax * dgh::kScanBlocks * i4);
 }
 
 template <class V>
@@ -455,6 +461,7 @@ void fill_levels(dgh_ctx* c) {
   a.N = m.N;
   a.Np = m.tet.Np;
   a.Nfp = m.tet.Nfp;
+  a.nqb3 = std::max(m.tet.Nfp, m.Ktri * m.tri.Np);
   a.ops = dptr<double>(c, L.ops3);
   a.fmask = dptr<int>(c, L.fmask3);
   a.fmap = dptr<int>(c, L.fmap3);
@@ -494,6 +501,7 @@ void fill_levels(dgh_ctx* c) {
   z.info = dptr<int>(c, L.info0);
   z.nrm = dptr<double>(c, L.nrm0);
   z.Tt = dptr<double>(c, L.T);
+  c->LB.ntri = dptr<int>(c, L.wntri);
   c->LB.tris = dptr<int>(c, L.wtris);
   c->LB.lines = dptr<int>(c, L.wlines);
   c->LB.corners = dptr<int>(c, L.wcorners);
@@ -645,6 +653,8 @@ dgh_status dgh_workspace_size(dgh_ctx* c, size_t* bytes) {
   if (!c || !bytes) return DGH_EINVAL;
   if (c->stage < S_MATERIAL) return fail(c, DGH_ESTATE, "workspace_size before set_material");
   compute_layout(c);
+  if (c->lay.q3[0].bytes > 0xffffffffull)
+    return fail(c, DGH_EINVAL, "3D state array exceeds 4 GiB (32-bit buffer offsets)");
   *bytes = c->lay.total;
   return DGH_OK;
 }
@@ -653,6 +663,8 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
   if (!c) return DGH_EINVAL;
   if (c->stage < S_MATERIAL) return fail(c, DGH_ESTATE, "bind before set_material");
   compute_layout(c);
+  if (c->lay.q3[0].bytes > 0xffffffffull)
+    return fail(c, DGH_EINVAL, "3D state array exceeds 4 GiB (32-bit buffer offsets)");
   if (!dev || bytes < c->lay.total) return fail(c, DGH_ENOMEM, "workspace too small");
   if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(c, DGH_EINVAL, "workspace not 256-byte aligned");
   HIPCHECK(c, hipSetDevice(c->device));
@@ -696,6 +708,7 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
       for (int k = 0; k < n3; ++k) Tt[(size_t)k * n3 + r] = c->habc.T[(size_t)r * n3 + k];
     HIPCHECK(c, upload(c, L.T, Tt));
   }
+  HIPCHECK(c, upload(c, L.wntri, c->wntri));
   HIPCHECK(c, upload(c, L.wtris, c->wtris));
   HIPCHECK(c, upload(c, L.wlines, c->wlines));
   HIPCHECK(c, upload(c, L.wcorners, c->wcorners));
@@ -883,6 +896,48 @@ dgh_status dgh_energy(dgh_ctx* c, int shot, double* e) {
   double s = 0.0;
   for (double v : part) s += v;
   *e = s;
+  return DGH_OK;
+}
+
+dgh_status dgh_check(dgh_ctx* c, int shot, double e_ref, double rel_tol, double* e_out) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "check before bind");
+  if (shot != 0) return fail(c, DGH_EINVAL, "shot out of range");
+  if (!(rel_tol >= 0.0)) return fail(c, DGH_EINVAL, "rel_tol must be >= 0");
+  const dgh::Mesh& m = c->mesh;
+  const Layout& L = c->lay;
+  const int cur = c->cur, P = c->P, Np = m.tet.Np;
+  const size_t n3 = (size_t)c->ntile * 4 * Np * dgh::kTile;
+  const Region* regs[] = {&L.q3[cur], &L.res3, &L.q2[cur], &L.res2, &L.qb3, &L.q03,
+                          &L.q1[cur], &L.res1, &L.qb2, &L.q02, &L.qb1};
+  const size_t ns[] = {n3, n3,
+                       (size_t)m.Ktri * P * 3 * m.tri.Np, (size_t)m.Ktri * P * 3 * m.tri.Np,
+                       (size_t)m.Ktri * m.tri.Np, (size_t)m.Ktri * m.tri.Np,
+                       (size_t)m.Klin * P * P * 2 * m.line.Np,
+                       (size_t)m.Klin * P * P * 2 * m.line.Np,
+                       (size_t)m.Klin * 2 * P * m.line.Np, (size_t)m.Klin * 2 * P * m.line.Np,
+                       (size_t)m.Kpnt * 3 * P * P};
+  dgh::ScanList sl{};
+  for (int a = 0; a < DGH_NARRAYS; ++a)
+    if (ns[a] > 0) {
+      sl.ptr[sl.count] = dptr<double>(c, *regs[a]);
+      sl.n[sl.count] = ns[a];
+      ++sl.count;
+    }
+  HIPCHECK(c, dgh::launch_nonfinite(sl, dptr<int>(c, L.flags), c->stream));
+  std::vector<int> fl((size_t)sl.count * dgh::kScanBlocks);
+  if (!fl.empty())
+    HIPCHECK(c, hipMemcpyAsync(fl.data(), c->ws + L.flags.off, fl.size() * sizeof(int),
+                               hipMemcpyDeviceToHost, c->stream));
+  double e = 0.0;
+  const dgh_status st = dgh_energy(c, shot, &e);  // synchronises the stream
+  if (st != DGH_OK) return st;
+  if (e_out) *e_out = e;
+  for (int f : fl)
+    if (f) return fail(c, DGH_ENONFINITE, "non-finite value in the state");
+  if (!std::isfinite(e)) return fail(c, DGH_ENONFINITE, "non-finite energy");
+  if (e_ref > 0.0 && e > e_ref * (1.0 + rel_tol))
+    return fail(c, DGH_EUNSTABLE, "energy grew beyond the reference");
   return DGH_OK;
 }
 

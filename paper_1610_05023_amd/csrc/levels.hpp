@@ -17,13 +17,14 @@ inline int frag3_size(int N) {
 
 // 3D level.  State layout [tile][field][node][16]; geometry [tile][12][16]:
 // rx ry rz sx sy sz tx ty tz 1/rho rho*c^2 rho*c; zn [tile][4][16] impedance
-// of the neighbour across each face; nbr [tile][4][16] face codes:
+// of the neighbour across each face (the element's own on boundary faces); nbr [tile][4][16] face codes:
 //   >= 0 : (e2 << 5) | (f2 << 3) | perm      interior face
 //   <  0 : -1 - ((t << 5) | (perm << 2) | bc) boundary; bc 0 = HABC
 //          (t = triangle, perm = vertex permutation to it), 1 = ABC,
 //          2 = Dirichlet
 struct Lvl3 {
   int K, ntile, N, Np, Nfp;
+  int nqb3;            // doubles in qb3 (>= Nfp)
   // A-fragments of the FP64 4x4x4 MFMA: Dr, Ds, Dt as [3][RG][RG][16] with
   // entry t = i + 4 k holding D[4 rg + i][4 ks + k], then LIFT as
   // [RG][4 faces][FK][16] with entry t holding LIFT[4 rg + i][f Nfp + 4 jj + k];
@@ -91,6 +92,7 @@ hipError_t launch_level3(const Lvl3& L, const double* qo, double* qn, double* re
 // triangle adjacent to their lines and every line of their corners.
 struct LvlB {
   int nblocks, TPB, NS, maxtri, maxlin, maxcor;
+  const int* ntri;     // triangles of each block
   const int* tris;
   const int* lines;
   const int* corners;
@@ -102,6 +104,17 @@ hipError_t launch_boundary(const LvlB& W, const Lvl2& L2, const Lvl1& L1, const 
                            double* qb2, double* qb3, double* q03, const double* q3n,
                            const double* q1o, double* q1n, double* res1, double* qb1,
                            double* q02, double A, double B, double dt, hipStream_t st);
+// Arrays scanned by the finiteness check (at most kScanMax of them); the
+// kernel writes one int per (array, block): 1 if a non-finite value was seen.
+constexpr int kScanMax = 12;
+constexpr int kScanBlocks = 256;
+struct ScanList {
+  const double* ptr[kScanMax];
+  size_t n[kScanMax];
+  int count;
+};
+hipError_t launch_nonfinite(const ScanList& s, int* flags, hipStream_t st);
+
 // FP64 energy partial sums: one value per tile written to out[ntile].
 hipError_t launch_energy(const Lvl3& L, const double* q, const double* mass, const double* J,
                          double* out, hipStream_t st);

@@ -18,31 +18,6 @@ namespace dgh {
 
 namespace {
 
-__device__ __forceinline__ void upwind(double pM, double unM, double ZM, double pP, double unP,
-                                       double ZP, double& pF, double& unF) {
-  // p* = ({p/Z} - n.[[u]]) / {1/Z}, (n.u)* = (n.{Z u} - [[p]]) / {Z}
-  const double iZ = 1.0 / (ZM + ZP);
-  pF = (ZP * pM + ZM * pP + ZM * ZP * (unM - unP)) * iZ;
-  unF = (pM - pP + ZM * unM + ZP * unP) * iZ;
-}
-
-__device__ __forceinline__ void charflux(double pM, double unM, double Z, double rm, double& pF,
-                                         double& unF) {
-  const double rp = 0.5 * (pM + Z * unM);
-  pF = rp + rm;
-  unF = (rp - rm) / Z;
-}
-
-__device__ __forceinline__ void bcflux(int bc, double pM, double unM, double Z, double rm,
-                                       double& pF, double& unF) {
-  if (bc == 2) {  // p = 0
-    pF = 0.0;
-    unF = unM + pM / Z;
-  } else {
-    charflux(pM, unM, Z, bc == 0 ? rm : 0.0, pF, unF);
-  }
-}
-
 // ------------------------------------------------------------------ 3D ---
 // One wave per tile of 16 elements.  The volume and lifting contractions run
 // on the FP64 4x4x4 MFMA (four 4x4x4 blocks per instruction; on gfx950 it
@@ -71,6 +46,24 @@ __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
+// Buffer-resource access: a 32-bit per-lane byte offset plus a uniform
+// (scalar) offset, so the four fields of a node share one address register.
+// The host keeps every 3D array below 4 GiB; an offset past the end of a
+// resource reads 0 (never used: every index is in range by construction).
+using Rsrc = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ Rsrc rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ double bld(Rsrc r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bst(Rsrc r, unsigned voff, unsigned soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+}
+
 // Maps the hardware block id to a logical block so that each XCD (blocks
 // are dealt round-robin over the 8 XCDs) walks a contiguous range of tiles:
 // neighbours of a tile then mostly sit in the same XCD's L2.
@@ -87,6 +80,8 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
                                                    const double* __restrict__ src_w, double src_s) {
   using D = Dims3<N>;
   constexpr int Np = D::Np, Nfp = D::Nfp, RG = D::RG, FK = D::FK;
+  constexpr unsigned FS = Np * kTile * 8;   // bytes between two fields of a tile
+  constexpr unsigned TS = 4 * FS;           // bytes per tile
   extern __shared__ double sfrag[];
   // face-node tables in LDS (first), then the operator fragments
   int* smask = reinterpret_cast<int*>(sfrag);
@@ -106,7 +101,10 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
   const double* frag = (D::kLds ? sops : L.ops) + ta;
   const double* fragL = frag + 3 * RG * RG * 16;
   const int e = tile * kTile + es;
-  const double* qt = qo + (size_t)tile * 4 * Np * kTile + es;
+  const unsigned nbytes = (unsigned)L.ntile * TS;
+  const Rsrc Rq = rsrc(qo, nbytes), Rn = rsrc(qn, nbytes), Rr = rsrc(res, nbytes);
+  const Rsrc Rb = rsrc(qb3, (unsigned)L.nqb3 * 8);
+  const unsigned tb = (unsigned)tile * TS + (unsigned)es * 8;   // this lane's element
   const double* gt = L.geo + (size_t)tile * 12 * kTile + es;
   const double rx = gt[0 * kTile], ry = gt[1 * kTile], rz = gt[2 * kTile];
   const double sx = gt[3 * kTile], sy = gt[4 * kTile], sz = gt[5 * kTile];
@@ -114,7 +112,8 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
   const double irho = gt[9 * kTile], Kb = gt[10 * kTile], Z = gt[11 * kTile];
 
   // ---- volume: Dr p, Ds p, Dt p and div u = Dr fr + Ds fs + Dt ft with the
-  // contravariant fluxes fr = grad r . u etc.
+  // contravariant fluxes fr = grad r . u etc.  Rows beyond Np read the last
+  // node (finite); the operator columns there are zero.
   double dpr[RG], dps[RG], dpt[RG], dv[RG];
 #pragma unroll
   for (int i = 0; i < RG; ++i) dpr[i] = dps[i] = dpt[i] = dv[i] = 0.0;
@@ -122,18 +121,13 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
   // N > 4, where the accumulators leave no registers for it)
   constexpr int PF = N <= 4 ? 3 : 1;
   double bp[PF], bu[PF], bv[PF], bw[PF];
-  // loads are issued unconditionally at clamped (in-range) nodes and masked
-  // afterwards, so that no load sits behind a divergent branch
 #pragma unroll
   for (int k = 0; k < PF; ++k) {
-    const int node = 4 * k + g;
-    const bool in = k < RG && node < Np;
-    const int nc = min(node, Np - 1);
-    bp[k] = qt[(0 * Np + nc) * kTile];
-    bu[k] = qt[(1 * Np + nc) * kTile];
-    bv[k] = qt[(2 * Np + nc) * kTile];
-    bw[k] = qt[(3 * Np + nc) * kTile];
-    if (!in) bp[k] = bu[k] = bv[k] = bw[k] = 0.0;
+    const unsigned o = tb + (unsigned)min(4 * k + g, Np - 1) * (kTile * 8);
+    bp[k] = bld(Rq, o, 0);
+    bu[k] = bld(Rq, o, FS);
+    bv[k] = bld(Rq, o, 2 * FS);
+    bw[k] = bld(Rq, o, 3 * FS);
   }
 #pragma unroll 1
   for (int j0 = 0; j0 < RG; j0 += PF) {
@@ -143,15 +137,11 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
       if (j < RG) {
         const double p = bp[sl], u = bu[sl], v = bv[sl], w = bw[sl];
         {
-          const int jn = j + PF, node = 4 * jn + g;
-          const bool in = jn < RG && node < Np;
-          const int nc = min(node, Np - 1);
-          const double a0 = qt[(0 * Np + nc) * kTile], a1 = qt[(1 * Np + nc) * kTile];
-          const double a2 = qt[(2 * Np + nc) * kTile], a3 = qt[(3 * Np + nc) * kTile];
-          bp[sl] = in ? a0 : 0.0;
-          bu[sl] = in ? a1 : 0.0;
-          bv[sl] = in ? a2 : 0.0;
-          bw[sl] = in ? a3 : 0.0;
+          const unsigned o = tb + (unsigned)min(4 * (j + PF) + g, Np - 1) * (kTile * 8);
+          bp[sl] = bld(Rq, o, 0);
+          bu[sl] = bld(Rq, o, FS);
+          bv[sl] = bld(Rq, o, 2 * FS);
+          bw[sl] = bld(Rq, o, 3 * FS);
         }
         const double fr = rx * u + ry * v + rz * w;
         const double fs = sx * u + sy * v + sz * w;
@@ -187,7 +177,13 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
   double* rv = dps;
   double* rw = dpt;
 
-  // ---- surface: fluxes at the face nodes in B-fragment order, then LIFT
+  // ---- surface: fluxes at the face nodes in B-fragment order, then LIFT.
+  // Every face uses the upwind flux against an exterior state: the
+  // neighbour's trace (interior), p = 2 r- and n.u = 0 (characteristic
+  // condition with incoming r-: HABC r- = qb3, basic ABC r- = 0), or the
+  // mirror p = -p^-, n.u = n.u^- (p = 0); boundary faces carry their own
+  // impedance, for which this reproduces the characteristic and Dirichlet
+  // fluxes exactly.
   const int* nbrt = L.nbr + tile * 4 * kTile + es;
   const double* znt = L.zn + tile * 4 * kTile + es;
 #pragma unroll 1
@@ -207,49 +203,44 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
     const int code = nbrt[f * kTile];
     const double ZP = znt[f * kTile];
     // interior faces gather from the neighbour; boundary faces read their own
-    // element there (ignored) and the HABC characteristic qb3 (triangle 0 for
-    // interior faces, ignored) -- every load is issued, then results selected
+    // element there (unused) and qb3 (triangle 0 unless HABC, unused) --
+    // every load is issued, then the exterior state is selected
     const bool inner = code >= 0;
     const int cb = -1 - code;
-    const int bc = inner ? -1 : (cb & 3);
+    const bool hb = !inner && (cb & 3) == 0;
+    const bool dir = !inner && (cb & 3) == 2;
     const int e2 = inner ? (code >> 5) : e;
-    const double* q2 = qo + (size_t)(e2 >> 4) * 4 * Np * kTile + (e2 & 15);
+    const unsigned nb = (unsigned)(e2 >> 4) * TS + (unsigned)(e2 & 15) * 8;
     const int mapbase = inner ? ((f * 4 + ((code >> 3) & 3)) * 6 + (code & 7)) * Nfp
                               : ((f * 4) * 6 + ((cb >> 2) & 7)) * Nfp;
-    const double* qbt = qb3 + (size_t)((!inner && bc == 0) ? (cb >> 5) : 0) * Nfp;
-    // upwind weights of this face (exact-Riemann flux, Section 3.2)
+    const unsigned qbo = (unsigned)(hb ? (cb >> 5) : 0) * (Nfp * 8);
+    // upwind weights (exact-Riemann flux, Section 3.2)
     const double iZ = 1.0 / (Z + ZP);
-    const double iZb = 1.0 / Z;
+    const double aM = ZP * iZ, aP = Z * iZ, bZ = Z * aM;
+    const double cP = fsc * Kb, cU = fsc * irho;
     double tmp[RG];
 #pragma unroll
     for (int i = 0; i < RG; ++i) tmp[i] = 0.0;
 #pragma unroll
     for (int jj = 0; jj < FK; ++jj) {
-      const int k = 4 * jj + g;
-      const int kc = min(k, Nfp - 1);
+      const int kc = min(4 * jj + g, Nfp - 1);   // rows beyond Nfp: LIFT columns are 0
       const int n = smask[f * Nfp + kc];
       const int n2 = smap[mapbase + kc];
-      const double pM = qt[n * kTile];
-      const double uM = qt[(Np + n) * kTile], vM = qt[(2 * Np + n) * kTile],
-                   wM = qt[(3 * Np + n) * kTile];
-      const double pP = q2[n2 * kTile];
-      const double uP = q2[(Np + n2) * kTile], vP = q2[(2 * Np + n2) * kTile],
-                   wP = q2[(3 * Np + n2) * kTile];
-      const double rb = qbt[min(n2, Nfp - 1)];
+      const unsigned oM = tb + (unsigned)n * (kTile * 8);
+      const unsigned oP = nb + (unsigned)n2 * (kTile * 8);
+      const double pM = bld(Rq, oM, 0), uM = bld(Rq, oM, FS), vM = bld(Rq, oM, 2 * FS),
+                   wM = bld(Rq, oM, 3 * FS);
+      const double pP = bld(Rq, oP, 0), uP = bld(Rq, oP, FS), vP = bld(Rq, oP, 2 * FS),
+                   wP = bld(Rq, oP, 3 * FS);
+      const double rb = bld(Rb, qbo + (unsigned)min(n2, Nfp - 1) * 8, 0);
       const double unM = nx * uM + ny * vM + nz * wM;
       const double unP = nx * uP + ny * vP + nz * wP;
-      // all three flux forms, then a select (no divergent branch)
-      const double pFi = (ZP * pM + Z * pP + Z * ZP * (unM - unP)) * iZ;   // upwind
-      const double unFi = (pM - pP + Z * unM + ZP * unP) * iZ;
-      const double rpl = 0.5 * (pM + Z * unM);                            // characteristic
-      const double rmi = bc == 0 ? rb : 0.0;
-      const double pFc = rpl + rmi, unFc = (rpl - rmi) * iZb;
-      const double unFd = unM + pM * iZb;                                // p = 0
-      const double pF = inner ? pFi : (bc == 2 ? 0.0 : pFc);
-      const double unF = inner ? unFi : (bc == 2 ? unFd : unFc);
-      const bool valid = k < Nfp;
-      const double fp = valid ? fsc * Kb * (unM - unF) : 0.0;
-      const double fu = valid ? fsc * irho * (pM - pF) : 0.0;
+      const double pG = inner ? pP : (dir ? -pM : (hb ? 2.0 * rb : 0.0));
+      const double uG = inner ? unP : (dir ? unM : 0.0);
+      const double pF = aM * pM + aP * pG + bZ * (unM - uG);
+      const double unF = iZ * (pM - pG) + aP * unM + aM * uG;
+      const double fp = cP * (unM - unF);
+      const double fu = cU * (pM - pF);
       const double* fl = fragL + (f * FK + jj) * 16;
 #pragma unroll
       for (int i = 0; i < RG; ++i) {
@@ -279,12 +270,11 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
       double ro[EC][4], qo_[EC][4];
 #pragma unroll
       for (int ii = 0; ii < EC; ++ii) {
-        const int nc = min(4 * (i0 + ii) + g, Np - 1);
+        const unsigned o = tb + (unsigned)min(4 * (i0 + ii) + g, Np - 1) * (kTile * 8);
 #pragma unroll
         for (int fl = 0; fl < 4; ++fl) {
-          const size_t idx = ((size_t)(tile * 4 + fl) * Np + nc) * kTile + es;
-          ro[ii][fl] = (i0 + ii < RG) ? res[idx] : 0.0;
-          qo_[ii][fl] = (i0 + ii < RG) ? qt[(fl * Np + nc) * kTile] : 0.0;
+          ro[ii][fl] = (i0 + ii < RG) ? bld(Rr, o, fl * FS) : 0.0;
+          qo_[ii][fl] = (i0 + ii < RG) ? bld(Rq, o, fl * FS) : 0.0;
         }
       }
 #pragma unroll
@@ -293,15 +283,15 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
         if (i >= RG) continue;
         const int n = 4 * i + g;
         const int nc = min(n, Np - 1);
+        const unsigned o = tb + (unsigned)nc * (kTile * 8);
         const double sw = src_w[nc];
         const double rhs[4] = {rp[i] + (src ? sw * src_s : 0.0), ru[i], rv[i], rw[i]};
         if (live && n < Np) {
 #pragma unroll
           for (int fl = 0; fl < 4; ++fl) {
-            const size_t idx = ((size_t)(tile * 4 + fl) * Np + n) * kTile + es;
             const double rr = A * ro[ii][fl] + dt * rhs[fl];
-            res[idx] = rr;
-            qn[idx] = qo_[ii][fl] + B * rr;
+            bst(Rr, o, fl * FS, rr);
+            bst(Rn, o, fl * FS, qo_[ii][fl] + B * rr);
           }
         }
       }

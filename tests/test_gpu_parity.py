@@ -110,3 +110,24 @@ def test_deterministic_rerun():
         out.append(s.read_fields())
     for k in out[0]:
         assert np.array_equal(out[0][k], out[1][k]), k
+
+
+def test_check_finite_and_energy():
+    """The failure check: clean state passes with its own energy as the
+    reference; a smaller reference reports growth; a NaN planted in a
+    boundary-level array (host input, valid for every kernel) is found."""
+    case = make_case(n=4, N=3, P=3, init="random", seed=61)
+    s = make_solver(case)
+    st, e = s.check()
+    case["oracle"].s = {k: v.copy() for k, v in case["state"].items()}
+    assert st == "DGH_OK" and abs(e - case["oracle"].energy()) <= 1e-12 * abs(e)
+    assert s.check(e_ref=e, rel_tol=1e-12)[0] == "DGH_OK"
+    assert s.check(e_ref=0.5 * e, rel_tol=0.1)[0] == "DGH_EUNSTABLE"
+    for name in ("q3", "res2", "qb2", "qb1"):
+        bad = {k: v.copy() for k, v in case["state"].items()}
+        bad[name].reshape(-1)[bad[name].size // 2] = np.nan
+        s.set_state(bad)
+        assert s.check()[0] == "DGH_ENONFINITE", name
+    s.set_state(case["state"])
+    s.step(5, 1e-3)
+    assert s.check()[0] == "DGH_OK"
