@@ -78,7 +78,11 @@ enum {
 };
 
 /* Creates a context for HIP device `device`.  precision: DGH_FP64.
- * n_shots: number of independent right-hand sides stepped together (1). */
+ * n_shots (1..4096): independent problems on the same mesh and medium,
+ * each with its own state and point source, stepped together: every launch
+ * covers all shots (the operators, geometry and maps are shared).  Each
+ * state array is allocated per shot; a shot's 3D state must stay below
+ * 4 GiB. */
 dgh_status dgh_create(dgh_ctx** out, int device, int precision, int n_shots);
 
 /* Tetrahedral mesh of the cuboid box = {lo[3], hi[3]} (Section 3.2: volume
@@ -115,7 +119,8 @@ dgh_status dgh_workspace_size(dgh_ctx* ctx, size_t* bytes);
  * maps; zeroes the state.  `stream` is a hipStream_t (NULL = default). */
 dgh_status dgh_bind_workspace(dgh_ctx* ctx, void* device_ptr, size_t bytes, void* stream);
 
-/* Sets the state of one shot from host arrays in the canonical layouts;
+/* Sets the state of one shot (0 <= shot < n_shots) from host arrays in the
+ * canonical layouts;
  * arrays[DGH_NARRAYS], a NULL entry means zeros.  Synchronises the stream. */
 dgh_status dgh_set_state(dgh_ctx* ctx, int shot, const double* const* arrays);
 

@@ -44,6 +44,14 @@ __device__ __forceinline__ void bcflux2(int bc, double pM, double unM, double Z,
   }
 }
 
+// Per-node inputs of the 1D update, loaded before any store of the phase.
+struct LineNode {
+  bool on;
+  int s, a;
+  double ro0, ro1, SA, SB;
+  double xp[2], xw[2], xz[2], xr[2];
+};
+
 struct Bufs {
   const double* q2o;
   double *q2n, *res2, *qb2, *qb3, *q03;
@@ -52,22 +60,45 @@ struct Bufs {
   double *q1n, *res1, *qb1, *q02;
 };
 
-__global__ void __launch_bounds__(512) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0 L0, Lvl3 L3,
-                                                  Bufs b, double A, double B, double dt) {
+template <int NPT>
+__global__ void __launch_bounds__(512, 4) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0 L0, int np3,
+                                                     Bufs b, Shots sh, double A, double B,
+                                                     double dt) {
   extern __shared__ double smem[];
+  {
+    // this block's shot
+    const size_t k = blockIdx.y;
+    b.q2o += k * sh.st2;
+    b.q2n += k * sh.st2;
+    b.res2 += k * sh.st2;
+    b.qb3 += k * sh.stb3;
+    b.q03 += k * sh.stb3;
+    b.q3n += k * sh.st3;
+    b.q1o += k * sh.st1;
+    b.q1n += k * sh.st1;
+    b.res1 += k * sh.st1;
+    b.qb2 += k * sh.stb2;
+    b.q02 += k * sh.stb2;
+    b.qb1 += k * sh.stb1;
+  }
   const int P = L2.P, Pe = P > 0 ? P : 1;
   const int tid = threadIdx.x, nth = blockDim.x, blk = blockIdx.x;
+  // Every phase issues all of a thread's global loads before its first
+  // global store, so that they are in flight together (the state arrays may
+  // alias as far as the compiler knows); small constant tables sit in LDS.
   // ---------------------------------------------------------------- 2D ----
   {
     const int Np = L2.Np, Nfp = L2.Nfp, NE = 3 * Nfp, NS = W.NS, TPB = W.TPB;
     double* sDr = smem;
     double* sDs = sDr + Np * Np;
     double* sL = sDs + Np * Np;                 // Np x NE
-    double* sq = sL + Np * NE;                  // TPB x P x 3 x Np
+    double* sg = sL + Np * NE;                  // P: gamma
+    double* sq = sg + Pe;                       // TPB x P x 3 x Np
     double* sf = sq + TPB * P * 3 * Np;         // TPB x P x 2 x NE
     double* sps = sf + TPB * P * 2 * NE;        // TPB x P x Np
     double* sS = sps + TPB * P * Np;            // TPB x Np
     for (int x = tid; x < 2 * Np * Np + Np * NE; x += nth) sDr[x] = L2.ops[x];
+    for (int x = tid; x < P; x += nth) sg[x] = L2.gamma[x];
     const int per = Pe * NS;
     const int tl = tid / per, rem = tid - tl * per, i = rem / NS, slot = rem - i * NS;
     const int ntri = W.ntri[blk];
@@ -85,9 +116,8 @@ __global__ void __launch_bounds__(512) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0
         for (int k = 0; k < 6; ++k) info[k] = L2.info[t * 8 + k];
       }
       const bool act = t >= 0 && i < P;
-      // loads of this thread that do not depend on the tile: the previous
-      // residual and q0 of its node, the new 3D trace for the face rule, and
-      // the neighbour's trace (or the edge characteristic) of its edge node
+      // the previous residual and q0 of this thread's node, the new 3D trace
+      // for the face rule, and the exterior values of its edge node
       double r0 = 0, r1 = 0, r2 = 0, S0 = 0, p3 = 0, u3 = 0;
       if (act && slot < Np) {
         const size_t base = ((size_t)t * P + i) * 3 * Np + slot;
@@ -98,17 +128,18 @@ __global__ void __launch_bounds__(512) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0
       }
       if (t >= 0 && i == 0 && slot < Np) {
         const int e = info[0], n3 = L2.tetnode[(size_t)t * Np + slot];
-        const double* q3 = b.q3n + (size_t)(e >> 4) * 4 * L3.Np * kTile + (e & 15);
+        const double* q3 = b.q3n + (size_t)(e >> 4) * 4 * np3 * kTile + (e & 15);
         p3 = q3[n3 * kTile];
-        u3 = q3[((1 + info[1]) * L3.Np + n3) * kTile];
+        u3 = q3[((1 + info[1]) * np3 + n3) * kTile];
       }
-      int ef = 0, ek = 0, code = 0, nn = 0;
+      int ef = 0, ek = 0, code = 0, nn = 0, fa = 0;
       double gP = 0, gA = 0, gB = 0, gZ = 1, grm = 0;
       if (act && slot < NE) {
         ef = slot / Nfp;
         ek = slot - ef * Nfp;
         code = info[3 + ef];
         nn = L2.nbrnode[(t * 3 + ef) * Nfp + ek];
+        fa = L2.fmask[ef * Nfp + ek];
         if (code >= 0) {
           const double* q = b.q2o + ((size_t)code * P + i) * 3 * Np;
           gP = q[nn];
@@ -133,13 +164,12 @@ __global__ void __launch_bounds__(512) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0
           en[f][1] = t >= 0 ? v[f][1] / m : 0.0;
         }
       }
-      const double Ki = act ? Kb / (1.0 + L2.gamma[i]) : 0.0;
+      const double Ki = act ? Kb / (1.0 + sg[i]) : 0.0;
       // ---- fluxes on the 3 edges
       if (act && slot < NE) {
-        const int a = L2.fmask[ef * Nfp + ek];
         const double na = en[ef][0], nb = en[ef][1];
-        const double pM = sqt[a];
-        const double vnM = na * sqt[Np + a] + nb * sqt[2 * Np + a];
+        const double pM = sqt[fa];
+        const double vnM = na * sqt[Np + fa] + nb * sqt[2 * Np + fa];
         double pF, vnF;
         if (code >= 0)
           upwind2(pM, vnM, Z, gP, na * gA + nb * gB, gZ, pF, vnF);
@@ -192,7 +222,7 @@ __global__ void __launch_bounds__(512) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0
         const int a = slot;
         const double rp = 0.5 * (p3 + Z * (double)info[2] * u3);
         double rm = 0.0;
-        for (int s = 0; s < P; ++s) rm += L2.gamma[s] * sps[(tl * P + s) * Np + a];
+        for (int s = 0; s < P; ++s) rm += sg[s] * sps[(tl * P + s) * Np + a];
         rm *= L2.invM;
         const double S = rp + rm;
         b.qb3[(size_t)t * Np + a] = rm;
@@ -206,16 +236,39 @@ __global__ void __launch_bounds__(512) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0
   }
   if (W.maxlin == 0 || W.lines[blk * W.maxlin] < 0 || P == 0) return;
   // ---------------------------------------------------------------- 1D ----
-  const int PP = P * P, Np = L1.Np;
-  double* sq = smem;                   // PP x 2 x Np  (this line, old)
+  const int PP = P * P, Np = L1.Np, n2 = 2 * P, n3 = 3 * PP, mc = W.maxcor;
+  double* cDr = smem;                  // Np x Np
+  double* cLF = cDr + Np * Np;         // Np x 2
+  double* cG = cLF + 2 * Np;           // 2P x 2P
+  double* cH = cG + n2 * n2;           // 2P x 2P
+  double* cCji = cH + n2 * n2;         // P x P
+  double* cCij = cCji + PP;            // P x P
+  double* cg = cCij + PP;              // P
+  double* sq = cg + P;                 // PP x 2 x Np  (this line, old)
   double* sps = sq + PP * 2 * Np;      // PP x Np      (new p*)
   double* sw = sps + PP * Np;          // PP x Np      (new w)
   double* srp = sw + PP * Np;          // 2P x Np
-  double* sb = srp + 2 * P * Np;       // 2P x Np
-  double* sS = sb + 2 * P * Np;        // 2P x Np
-  double* sC = sS + 2 * P * Np;        // maxcor x 3 x PP x 2 (corner ends: p, w)
-  const double* Dr = L1.ops;
-  const double* LF = L1.ops + Np * Np;
+  double* sb = srp + n2 * Np;          // 2P x Np
+  double* sS = sb + n2 * Np;           // 2P x Np
+  double* sC = sS + n2 * Np;           // maxcor x 3 x PP x 2 (corner ends: p, w)
+  double* srp0 = sC + mc * 3 * PP * 2; // 3 PP
+  double* sred = srp0 + n3;            // nth partial sums of the corner systems
+  int* cInfo = reinterpret_cast<int*>(sred + nth);   // maxcor x 3: line << 1 | end
+  __syncthreads();   // the 2D phase is done with its LDS
+  for (int x = tid; x < Np * Np + 2 * Np; x += nth) cDr[x] = L1.ops[x];
+  for (int x = tid; x < n2 * n2; x += nth) {
+    cG[x] = L1.G[x];
+    cH[x] = L1.H[x];
+  }
+  for (int x = tid; x < PP; x += nth) {
+    cCji[x] = L1.Cji[x];
+    cCij[x] = L1.Cij[x];
+  }
+  for (int x = tid; x < P; x += nth) cg[x] = L1.gamma[x];
+  for (int x = tid; x < mc * 3; x += nth) {
+    const int c = W.corners[blk * mc + x / 3];
+    cInfo[x] = c < 0 ? -1 : (L0.info[(c * 3 + x % 3) * 2] << 1) | L0.info[(c * 3 + x % 3) * 2 + 1];
+  }
   for (int li = 0; li < W.maxlin; ++li) {
     const int l = W.lines[blk * W.maxlin + li];
     if (l < 0) break;
@@ -223,16 +276,54 @@ __global__ void __launch_bounds__(512) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0
     for (int x = tid; x < PP * 2 * Np; x += nth) sq[x] = b.q1o[(size_t)l * PP * 2 * Np + x];
     const double rx = L1.geo[l * 4 + 0], irho = L1.geo[l * 4 + 1], Kb = L1.geo[l * 4 + 2],
                  Z = L1.geo[l * 4 + 3];
-    const int* info = L1.info + l * 8;
+    int info[8];
+    for (int k = 0; k < 8; ++k) info[k] = L1.info[l * 8 + k];
+    // loads of this thread's nodes (x = tid + h nth, h < NPT: NPT nth >=
+    // P^2 Np1): old residuals, q0 of both faces, and the exterior values at
+    // both line ends (neighbour line or corner r-)
+    LineNode nd[NPT];
+#pragma unroll
+    for (int h = 0; h < NPT; ++h) {
+      LineNode& v = nd[h];
+      const int x = tid + h * nth;
+      v.on = x < PP * Np;
+      v.s = v.on ? x / Np : 0;
+      v.a = v.on ? x - v.s * Np : 0;
+      if (v.on) {
+        const int i = v.s / P, j = v.s - i * P;
+        const size_t base = (((size_t)l * PP + v.s) * 2) * Np + v.a;
+        v.ro0 = b.res1[base];
+        v.ro1 = b.res1[base + Np];
+        v.SA = b.q02[(((size_t)l * 2 + 0) * P + i) * Np + v.a];
+        v.SB = b.q02[(((size_t)l * 2 + 1) * P + j) * Np + v.a];
+        for (int end = 0; end < 2; ++end) {
+          const int code = info[4 + end];
+          v.xp[end] = v.xw[end] = v.xr[end] = 0.0;
+          v.xz[end] = 1.0;
+          if (code >= 0) {
+            const int l2 = code >> 1, node2 = (code & 1) ? Np - 1 : 0;
+            const double* q = b.q1o + (((size_t)l2 * PP + v.s) * 2) * Np;
+            v.xp[end] = q[node2];
+            v.xw[end] = q[Np + node2];
+            v.xz[end] = L1.geo[l2 * 4 + 3];
+          } else {
+            const int c = -1 - code, cs = (c >> 2) & 3, corner = c >> 4;
+            if ((c & 3) == 0) v.xr[end] = b.qb1[((size_t)corner * 3 + cs) * PP + v.s];
+          }
+        }
+      }
+    }
     __syncthreads();
-    for (int x = tid; x < PP * Np; x += nth) {
-      const int s = x / Np, a = x - s * Np;
-      const int i = s / P, j = s - i * P;
-      const double Kij = Kb / (1.0 + L1.gamma[i] + L1.gamma[j]);
+#pragma unroll
+    for (int h = 0; h < NPT; ++h) {
+      const LineNode& v = nd[h];
+      if (!v.on) continue;
+      const int s = v.s, a = v.a, i = s / P, j = s - i * P;
+      const double Kij = Kb / (1.0 + cg[i] + cg[j]);
       double px = 0, wx = 0;
       for (int m = 0; m < Np; ++m) {
-        px += Dr[a * Np + m] * sq[(s * 2) * Np + m];
-        wx += Dr[a * Np + m] * sq[(s * 2 + 1) * Np + m];
+        px += cDr[a * Np + m] * sq[(s * 2) * Np + m];
+        wx += cDr[a * Np + m] * sq[(s * 2 + 1) * Np + m];
       }
       px *= rx;
       wx *= rx;
@@ -245,101 +336,103 @@ __global__ void __launch_bounds__(512) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0
         const double wnM = n * sq[(s * 2 + 1) * Np + node];
         const int code = info[4 + end];
         double pF, wnF;
-        if (code >= 0) {
-          const int l2 = code >> 1, node2 = (code & 1) ? Np - 1 : 0;
-          const double* q = b.q1o + (((size_t)l2 * PP + s) * 2) * Np;
-          upwind2(pM, wnM, Z, q[node2], n * q[Np + node2], L1.geo[l2 * 4 + 3], pF, wnF);
-        } else {
-          const int c = -1 - code, bc = c & 3, cs = (c >> 2) & 3, corner = c >> 4;
-          const double rm = bc == 0 ? b.qb1[((size_t)corner * 3 + cs) * PP + s] : 0.0;
-          bcflux2(bc, pM, wnM, Z, rm, pF, wnF);
-        }
-        rhs0 += LF[a * 2 + end] * fsc * Kij * (wnM - wnF);
-        rhs1 += LF[a * 2 + end] * fsc * irho * (pM - pF) * n;
+        if (code >= 0)
+          upwind2(pM, wnM, Z, v.xp[end], n * v.xw[end], v.xz[end], pF, wnF);
+        else
+          bcflux2((-1 - code) & 3, pM, wnM, Z, v.xr[end], pF, wnF);
+        rhs0 += cLF[a * 2 + end] * fsc * Kij * (wnM - wnF);
+        rhs1 += cLF[a * 2 + end] * fsc * irho * (pM - pF) * n;
       }
       const size_t base = (((size_t)l * PP + s) * 2) * Np + a;
-      double r = A * b.res1[base] + dt * rhs0;
-      b.res1[base] = r;
-      const double SA = b.q02[(((size_t)l * 2 + 0) * P + i) * Np + a];
-      const double SB = b.q02[(((size_t)l * 2 + 1) * P + j) * Np + a];
-      sps[s * Np + a] = sq[(s * 2) * Np + a] - L1.Cji[i * P + j] * SA - L1.Cij[i * P + j] * SB + B * r;
-      r = A * b.res1[base + Np] + dt * rhs1;
-      b.res1[base + Np] = r;
-      const double wn = sq[(s * 2 + 1) * Np + a] + B * r;
+      const double r0 = A * v.ro0 + dt * rhs0, r1 = A * v.ro1 + dt * rhs1;
+      b.res1[base] = r0;
+      b.res1[base + Np] = r1;
+      sps[s * Np + a] = sq[(s * 2) * Np + a] - cCji[i * P + j] * v.SA - cCij[i * P + j] * v.SB + B * r0;
+      const double wn = sq[(s * 2 + 1) * Np + a] + B * r1;
       b.q1n[base + Np] = wn;
       sw[s * Np + a] = wn;
     }
     __syncthreads();
     // outgoing 2D characteristics (new 2D traces, written by this block) and b
-    for (int x = tid; x < 2 * P * Np; x += nth) {
-      const int row = x / Np, a = x - row * Np;
-      const int side = row / P, i = row - side * P;
+    for (int y = tid; y < n2 * Np; y += nth) {
+      const int row = y / Np, c = y - row * Np;
+      const int side = row / P, ii = row - side * P;
       const int t = info[side], comp = info[2 + side];
-      const int node = L1.trinode[((size_t)l * 2 + side) * Np + a];
-      const double* q = b.q2n + ((size_t)t * P + i) * 3 * L2.Np;
+      const int node = L1.trinode[((size_t)l * 2 + side) * Np + c];
+      const double* q = b.q2n + ((size_t)t * P + ii) * 3 * L2.Np;
       const double sgn = comp > 0 ? 1.0 : -1.0;
       const int cc = comp > 0 ? comp : -comp;
-      srp[row * Np + a] = 0.5 * (q[node] + L2.geo[(size_t)t * 8 + 6] * sgn * q[cc * L2.Np + node]);
+      const double zt = L2.geo[(size_t)t * 8 + 6];
+      const double pv = q[node], uv = q[cc * L2.Np + node];
       double bb = 0.0;
       if (side == 0)
-        for (int j = 0; j < P; ++j) bb += L1.gamma[j] * sps[(i * P + j) * Np + a];
+        for (int jj = 0; jj < P; ++jj) bb += cg[jj] * sps[(ii * P + jj) * Np + c];
       else
-        for (int ii = 0; ii < P; ++ii) bb += L1.gamma[ii] * sps[(ii * P + i) * Np + a];
-      sb[row * Np + a] = bb * L1.invM;
+        for (int i2 = 0; i2 < P; ++i2) bb += cg[i2] * sps[(i2 * P + ii) * Np + c];
+      sb[row * Np + c] = bb * L1.invM;
+      srp[row * Np + c] = 0.5 * (pv + zt * sgn * uv);
     }
     __syncthreads();
     // edge system r- = G r+ + H b
-    for (int x = tid; x < 2 * P * Np; x += nth) {
-      const int row = x / Np, a = x - row * Np;
-      const int n2 = 2 * P;
+    for (int y = tid; y < n2 * Np; y += nth) {
+      const int row = y / Np, c = y - row * Np;
       double rm = 0.0;
       for (int k = 0; k < n2; ++k)
-        rm += L1.G[row * n2 + k] * srp[k * Np + a] + L1.H[row * n2 + k] * sb[k * Np + a];
-      const int side = row / P, i = row - side * P;
-      const size_t o = (((size_t)l * 2 + side) * P + i) * Np + a;
+        rm += cG[row * n2 + k] * srp[k * Np + c] + cH[row * n2 + k] * sb[k * Np + c];
+      const int side = row / P, ii = row - side * P;
+      const size_t o = (((size_t)l * 2 + side) * P + ii) * Np + c;
       b.qb2[o] = rm;
-      const double S = srp[row * Np + a] + rm;
+      const double S = srp[row * Np + c] + rm;
       b.q02[o] = S;
-      sS[row * Np + a] = S;
+      sS[row * Np + c] = S;
     }
     __syncthreads();
-    for (int x = tid; x < PP * Np; x += nth) {
-      const int s = x / Np, a = x - s * Np;
-      const int i = s / P, j = s - i * P;
-      const double p = sps[s * Np + a] + L1.Cji[i * P + j] * sS[i * Np + a] +
-                       L1.Cij[i * P + j] * sS[(P + j) * Np + a];
+#pragma unroll
+    for (int h = 0; h < NPT; ++h) {
+      const LineNode& v = nd[h];
+      if (!v.on) continue;
+      const int s = v.s, a = v.a, i = s / P, j = s - i * P;
+      const double p = sps[s * Np + a] + cCji[i * P + j] * sS[i * Np + a] +
+                       cCij[i * P + j] * sS[(P + j) * Np + a];
       b.q1n[(((size_t)l * PP + s) * 2) * Np + a] = p;
       // keep the corner-end values for the corner systems of this block
-      if (a == 0 || a == Np - 1)
-        for (int ci = 0; ci < W.maxcor; ++ci) {
-          const int c = W.corners[blk * W.maxcor + ci];
-          if (c < 0) break;
-          for (int cs = 0; cs < 3; ++cs)
-            if (L0.info[(c * 3 + cs) * 2] == l && (L0.info[(c * 3 + cs) * 2 + 1] ? Np - 1 : 0) == a) {
-              sC[((ci * 3 + cs) * PP + s) * 2] = p;
-              sC[((ci * 3 + cs) * PP + s) * 2 + 1] = sw[s * Np + a];
-            }
-        }
+      if (a == 0 || a == Np - 1) {
+        const int key = (l << 1) | (a == 0 ? 0 : 1);
+        for (int y = 0; y < mc * 3; ++y)
+          if (cInfo[y] == key) {
+            sC[(y * PP + s) * 2] = p;
+            sC[(y * PP + s) * 2 + 1] = sw[s * Np + a];
+          }
+      }
     }
   }
   // ---------------------------------------------------------------- 0D ----
-  double* srp0 = sC + W.maxcor * 3 * PP * 2;   // 3 PP
-  const int n3 = 3 * PP;
-  for (int ci = 0; ci < W.maxcor; ++ci) {
-    const int c = W.corners[blk * W.maxcor + ci];
+  // r- = T r+ with the 3P^2 x 3P^2 corner map; the products are split over
+  // the block (nparts partial sums per output) and reduced in LDS
+  const int nparts = nth / n3 > 0 ? nth / n3 : 1;
+  for (int ci = 0; ci < mc; ++ci) {
+    const int c = W.corners[blk * mc + ci];
     if (c < 0) break;
     __syncthreads();
-    for (int x = tid; x < n3; x += nth) {
-      const int cs = x / PP;
-      const int l = L0.info[(c * 3 + cs) * 2];
-      srp0[x] = 0.5 * (sC[(ci * 3 * PP + x) * 2] +
-                       L1.geo[l * 4 + 3] * L0.nrm[c * 3 + cs] * sC[(ci * 3 * PP + x) * 2 + 1]);
+    for (int y = tid; y < n3; y += nth) {
+      const int cs = y / PP;
+      const int l = cInfo[ci * 3 + cs] >> 1;
+      srp0[y] = 0.5 * (sC[(ci * 3 * PP + y) * 2] +
+                       L1.geo[l * 4 + 3] * L0.nrm[c * 3 + cs] * sC[(ci * 3 * PP + y) * 2 + 1]);
     }
     __syncthreads();
-    for (int x = tid; x < n3; x += nth) {
+    for (int y = tid; y < n3 * nparts; y += nth) {
+      const int part = y / n3, xo = y - part * n3;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int k = part; k < n3; k += nparts) acc += L0.Tt[(size_t)k * n3 + xo] * srp0[k];
+      sred[y] = acc;
+    }
+    __syncthreads();
+    for (int y = tid; y < n3; y += nth) {
       double rm = 0.0;
-      for (int k = 0; k < n3; ++k) rm += L0.Tt[(size_t)k * n3 + x] * srp0[k];
-      b.qb1[(size_t)c * n3 + x] = rm;
+      for (int part = 0; part < nparts; ++part) rm += sred[part * n3 + y];
+      b.qb1[(size_t)c * n3 + y] = rm;
     }
   }
 }
@@ -350,22 +443,40 @@ hipError_t launch_boundary(const LvlB& W, const Lvl2& L2, const Lvl1& L1, const 
                            const Lvl3& L3, const double* q2o, double* q2n, double* res2,
                            double* qb2, double* qb3, double* q03, const double* q3n,
                            const double* q1o, double* q1n, double* res1, double* qb1,
-                           double* q02, double A, double B, double dt, hipStream_t st) {
+                           double* q02, double A, double B, double dt, const Shots& sh,
+                           hipStream_t st) {
   if (W.nblocks == 0) return hipSuccess;
+  if (sh.n < 1 || sh.n > 65535) return hipErrorInvalidValue;
   const int P = L2.P, Np2 = L2.Np, NE = 3 * L2.Nfp, TPB = W.TPB, Np1 = L1.Np, PP = P * P;
-  const size_t a2 = 2 * Np2 * Np2 + Np2 * NE + TPB * P * 3 * Np2 + TPB * P * 2 * NE +
+  const int Pe = P > 0 ? P : 1, n2 = 2 * P, n3 = 3 * PP;
+  const size_t a2 = 2 * Np2 * Np2 + Np2 * NE + Pe + TPB * P * 3 * Np2 + TPB * P * 2 * NE +
                     TPB * P * Np2 + TPB * Np2;
-  const size_t a1 = PP * 2 * Np1 + 2 * PP * Np1 + 6 * P * Np1 + W.maxcor * 3 * PP * 2 + 3 * PP;
+  const size_t a1 = Np1 * Np1 + 2 * Np1 + 2 * n2 * n2 + 2 * PP + P + PP * 2 * Np1 +
+                    2 * PP * Np1 + 3 * n2 * Np1 + W.maxcor * 3 * PP * 2 + n3 + 512 +
+                    (W.maxcor * 3 + 1) / 2 + 1;
   const size_t lds = sizeof(double) * (a2 > a1 ? a2 : a1);
-  static size_t attr = 0;
-  if (lds > attr) {
-    hipFuncSetAttribute((const void*)k_boundary, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-    attr = lds;
-  }
   Bufs b{q2o, q2n, res2, qb2, qb3, q03, q3n, q1o, q1n, res1, qb1, q02};
-  hipLaunchKernelGGL(k_boundary, dim3(W.nblocks), dim3(512), lds, st, W, L2, L1, L0, L3, b, A, B,
-                     dt);
+  // one edge node per thread unless P^2 Np1 exceeds the block (P > 10)
+  if (PP * Np1 <= 512) {
+    static size_t attr = 0;
+    if (lds > attr) {
+      (void)hipFuncSetAttribute((const void*)k_boundary<1>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      attr = lds;
+    }
+    hipLaunchKernelGGL(k_boundary<1>, dim3(W.nblocks, sh.n), dim3(512), lds, st, W, L2, L1, L0, L3.Np,
+                       b, sh, A, B, dt);
+  } else {
+    if (PP * Np1 > 1024) return hipErrorInvalidValue;
+    static size_t attr = 0;
+    if (lds > attr) {
+      (void)hipFuncSetAttribute((const void*)k_boundary<2>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      attr = lds;
+    }
+    hipLaunchKernelGGL(k_boundary<2>, dim3(W.nblocks, sh.n), dim3(512), lds, st, W, L2, L1, L0, L3.Np,
+                       b, sh, A, B, dt);
+  }
   return hipGetLastError();
 }
 

@@ -37,7 +37,9 @@ struct Layout {
   Region q3[2], res3, geo3, zn3, nbr3, ops3, fmask3, fmap3, mass3, J3, esum;
   Region q2[2], res2, qb3, q03, geo2, info2, tetnode2, nbrnode2, ops2, fmask2, gamma;
   Region q1[2], res1, qb2, q02, geo1, info1, trinode1, ops1, cji, cij, G, H;
-  Region qb1, info0, nrm0, T, srcw, wntri, wtris, wlines, wcorners, flags;
+  Region qb1, info0, nrm0, T, srcw, srcp, wntri, wtris, wlines, wcorners, flags;
+  // per-shot strides (doubles) of the state arrays
+  size_t st3 = 0, st2 = 0, stb3 = 0, st1 = 0, stb2 = 0, stb1 = 0;
   Region* add(Region& r, size_t bytes) {
     r.off = total;
     r.bytes = bytes;
@@ -65,9 +67,8 @@ struct dgh_ctx {
   int ntile = 0;
   std::vector<int> slot2elem, elem2slot;  // element order of the 3D layout
   bool structured = false;
-  // source
-  int src_elem = -1;
-  double f0 = 0, t0 = 0, amp = 0;
+  // point source of each shot: slot of its element (-1: none)
+  std::vector<int> src_slot;
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;   // pairs (start, stop) per timed launch
@@ -383,16 +384,25 @@ void build_host_arrays(dgh_ctx* c, HostArrays& h) {
     }
 }
 
+size_t round32(size_t n) { return (std::max<size_t>(n, 1) + 31) / 32 * 32; }
+
 void compute_layout(dgh_ctx* c) {
   const dgh::Mesh& m = c->mesh;
   Layout& L = c->lay;
   L = Layout{};
   const int Np = m.tet.Np, Nfp = m.tet.Nfp, nt = c->ntile, T = dgh::kTile, P = c->P;
-  const size_t d = sizeof(double), i4 = sizeof(int);
-  const size_t s3 = (size_t)nt * 4 * Np * T * d;
-  L.add(L.q3[0], s3);
-  L.add(L.q3[1], s3);
-  L.add(L.res3, s3);
+  const size_t d = sizeof(double), i4 = sizeof(int), S = (size_t)c->n_shots;
+  // every state array holds n_shots shots, each starting 256-byte aligned
+  const int Kt = m.Ktri, Np2 = m.tri.Np, Nfp2 = m.tri.Nfp, Kl = m.Klin, Np1 = m.line.Np;
+  L.st3 = round32((size_t)nt * 4 * Np * T);
+  L.st2 = round32((size_t)Kt * P * 3 * Np2);
+  L.stb3 = round32(std::max<size_t>(Nfp, (size_t)Kt * Np2));  // >= one triangle (read masked)
+  L.st1 = round32((size_t)Kl * P * P * 2 * Np1);
+  L.stb2 = round32((size_t)Kl * 2 * P * Np1);
+  L.stb1 = round32((size_t)m.Kpnt * 3 * P * P);
+  L.add(L.q3[0], S * L.st3 * d);
+  L.add(L.q3[1], S * L.st3 * d);
+  L.add(L.res3, S * L.st3 * d);
   L.add(L.geo3, (size_t)nt * 12 * T * d);
   L.add(L.zn3, (size_t)nt * 4 * T * d);
   L.add(L.nbr3, (size_t)nt * 4 * T * i4);
@@ -402,13 +412,11 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.mass3, (size_t)Np * Np * d);
   L.add(L.J3, (size_t)nt * T * d);
   L.add(L.esum, (size_t)nt * d);
-  const int Kt = m.Ktri, Np2 = m.tri.Np, Nfp2 = m.tri.Nfp;
-  const size_t s2 = (size_t)std::max(1, Kt * P * 3 * Np2) * d;
-  L.add(L.q2[0], s2);
-  L.add(L.q2[1], s2);
-  L.add(L.res2, s2);
-  L.add(L.qb3, (size_t)std::max(Nfp, Kt * Np2) * d);  // >= one triangle (read masked)
-  L.add(L.q03, (size_t)std::max(1, Kt * Np2) * d);
+  L.add(L.q2[0], S * L.st2 * d);
+  L.add(L.q2[1], S * L.st2 * d);
+  L.add(L.res2, S * L.st2 * d);
+  L.add(L.qb3, S * L.stb3 * d);
+  L.add(L.q03, S * L.stb3 * d);
   L.add(L.geo2, (size_t)std::max(1, Kt * 8) * d);
   L.add(L.info2, (size_t)std::max(1, Kt * 8) * i4);
   L.add(L.tetnode2, (size_t)std::max(1, Kt * Np2) * i4);
@@ -416,13 +424,11 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.ops2, (size_t)(2 * Np2 * Np2 + Np2 * 3 * Nfp2) * d);
   L.add(L.fmask2, (size_t)3 * Nfp2 * i4);
   L.add(L.gamma, (size_t)std::max(1, P) * d);
-  const int Kl = m.Klin, Np1 = m.line.Np;
-  const size_t s1 = (size_t)std::max(1, Kl * P * P * 2 * Np1) * d;
-  L.add(L.q1[0], s1);
-  L.add(L.q1[1], s1);
-  L.add(L.res1, s1);
-  L.add(L.qb2, (size_t)std::max(1, Kl * 2 * P * Np1) * d);
-  L.add(L.q02, (size_t)std::max(1, Kl * 2 * P * Np1) * d);
+  L.add(L.q1[0], S * L.st1 * d);
+  L.add(L.q1[1], S * L.st1 * d);
+  L.add(L.res1, S * L.st1 * d);
+  L.add(L.qb2, S * L.stb2 * d);
+  L.add(L.q02, S * L.stb2 * d);
   L.add(L.geo1, (size_t)std::max(1, Kl * 4) * d);
   L.add(L.info1, (size_t)std::max(1, Kl * 8) * i4);
   L.add(L.trinode1, (size_t)std::max(1, Kl * 2 * Np1) * i4);
@@ -431,11 +437,12 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.cij, (size_t)std::max(1, P * P) * d);
   L.add(L.G, (size_t)std::max(1, 4 * P * P) * d);
   L.add(L.H, (size_t)std::max(1, 4 * P * P) * d);
-  L.add(L.qb1, (size_t)std::max(1, m.Kpnt * 3 * P * P) * d);
+  L.add(L.qb1, S * L.stb1 * d);
   L.add(L.info0, (size_t)std::max(1, m.Kpnt * 6) * i4);
   L.add(L.nrm0, (size_t)std::max(1, m.Kpnt * 3) * d);
   L.add(L.T, (size_t)std::max(1, 9 * P * P * P * P) * d);
-  L.add(L.srcw, (size_t)Np * d);
+  L.add(L.srcw, S * Np * d);
+  L.add(L.srcp, S * 4 * d);
   build_worklist(c);
   L.add(L.wntri, std::max<size_t>(1, c->wntri.size()) * i4);
   L.add(L.wtris, std::max<size_t>(1, c->wtris.size()) * i4);
@@ -539,7 +546,7 @@ extern "C" {
 dgh_status dgh_create(dgh_ctx** out, int device, int precision, int n_shots) {
   if (!out) return DGH_EINVAL;
   *out = nullptr;
-  if (precision != DGH_FP64 || n_shots != 1 || device < 0) return DGH_EINVAL;
+  if (precision != DGH_FP64 || n_shots < 1 || n_shots > 4096 || device < 0) return DGH_EINVAL;
   dgh_ctx* c = new (std::nothrow) dgh_ctx();
   if (!c) return DGH_ENOMEM;
   c->device = device;
@@ -653,8 +660,8 @@ dgh_status dgh_workspace_size(dgh_ctx* c, size_t* bytes) {
   if (!c || !bytes) return DGH_EINVAL;
   if (c->stage < S_MATERIAL) return fail(c, DGH_ESTATE, "workspace_size before set_material");
   compute_layout(c);
-  if (c->lay.q3[0].bytes > 0xffffffffull)
-    return fail(c, DGH_EINVAL, "3D state array exceeds 4 GiB (32-bit buffer offsets)");
+  if (c->lay.st3 * sizeof(double) > 0xffffffffull)
+    return fail(c, DGH_EINVAL, "3D state of a shot exceeds 4 GiB (32-bit buffer offsets)");
   *bytes = c->lay.total;
   return DGH_OK;
 }
@@ -663,8 +670,8 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
   if (!c) return DGH_EINVAL;
   if (c->stage < S_MATERIAL) return fail(c, DGH_ESTATE, "bind before set_material");
   compute_layout(c);
-  if (c->lay.q3[0].bytes > 0xffffffffull)
-    return fail(c, DGH_EINVAL, "3D state array exceeds 4 GiB (32-bit buffer offsets)");
+  if (c->lay.st3 * sizeof(double) > 0xffffffffull)
+    return fail(c, DGH_EINVAL, "3D state of a shot exceeds 4 GiB (32-bit buffer offsets)");
   if (!dev || bytes < c->lay.total) return fail(c, DGH_ENOMEM, "workspace too small");
   if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(c, DGH_EINVAL, "workspace not 256-byte aligned");
   HIPCHECK(c, hipSetDevice(c->device));
@@ -714,7 +721,12 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
   HIPCHECK(c, upload(c, L.wcorners, c->wcorners));
   fill_levels(c);
   c->cur = 0;
-  c->src_elem = -1;
+  c->src_slot.assign(c->n_shots, -1);
+  {
+    std::vector<double> par((size_t)c->n_shots * 4, 0.0);
+    for (int k = 0; k < c->n_shots; ++k) par[4 * k] = -1.0;
+    HIPCHECK(c, upload(c, L.srcp, par));
+  }
   c->stage = S_BOUND;
   return DGH_OK;
 }
@@ -722,7 +734,7 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
 dgh_status dgh_set_state(dgh_ctx* c, int shot, const double* const* arr) {
   if (!c) return DGH_EINVAL;
   if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "set_state before bind");
-  if (shot != 0) return fail(c, DGH_EINVAL, "shot out of range");
+  if (shot < 0 || shot >= c->n_shots) return fail(c, DGH_EINVAL, "shot out of range");
   const dgh::Mesh& m = c->mesh;
   const Layout& L = c->lay;
   const int Np = m.tet.Np;
@@ -733,24 +745,25 @@ dgh_status dgh_set_state(dgh_ctx* c, int shot, const double* const* arr) {
     const double* src = (arr && arr[which]) ? arr[which] : zero.data();
     to_tiles(src, buf.data(), c->slot2elem, Np);
     const Region& r = which == DGH_Q3 ? L.q3[cur] : L.res3;
-    HIPCHECK(c, hipMemcpy(c->ws + r.off, buf.data(), r.bytes, hipMemcpyHostToDevice));
+    HIPCHECK(c, hipMemcpy(c->ws + r.off + shot * L.st3 * sizeof(double), buf.data(),
+                          buf.size() * sizeof(double), hipMemcpyHostToDevice));
   }
-  struct Item { int idx; const Region* r; size_t n; };
+  struct Item { int idx; const Region* r; size_t n, stride; };
   const int P = c->P;
   const Item items[] = {
-      {DGH_Q2, &L.q2[cur], (size_t)m.Ktri * P * 3 * m.tri.Np},
-      {DGH_RES2, &L.res2, (size_t)m.Ktri * P * 3 * m.tri.Np},
-      {DGH_QB3, &L.qb3, (size_t)m.Ktri * m.tri.Np},
-      {DGH_Q03, &L.q03, (size_t)m.Ktri * m.tri.Np},
-      {DGH_Q1, &L.q1[cur], (size_t)m.Klin * P * P * 2 * m.line.Np},
-      {DGH_RES1, &L.res1, (size_t)m.Klin * P * P * 2 * m.line.Np},
-      {DGH_QB2, &L.qb2, (size_t)m.Klin * 2 * P * m.line.Np},
-      {DGH_Q02, &L.q02, (size_t)m.Klin * 2 * P * m.line.Np},
-      {DGH_QB1, &L.qb1, (size_t)m.Kpnt * 3 * P * P},
+      {DGH_Q2, &L.q2[cur], (size_t)m.Ktri * P * 3 * m.tri.Np, L.st2},
+      {DGH_RES2, &L.res2, (size_t)m.Ktri * P * 3 * m.tri.Np, L.st2},
+      {DGH_QB3, &L.qb3, (size_t)m.Ktri * m.tri.Np, L.stb3},
+      {DGH_Q03, &L.q03, (size_t)m.Ktri * m.tri.Np, L.stb3},
+      {DGH_Q1, &L.q1[cur], (size_t)m.Klin * P * P * 2 * m.line.Np, L.st1},
+      {DGH_RES1, &L.res1, (size_t)m.Klin * P * P * 2 * m.line.Np, L.st1},
+      {DGH_QB2, &L.qb2, (size_t)m.Klin * 2 * P * m.line.Np, L.stb2},
+      {DGH_Q02, &L.q02, (size_t)m.Klin * 2 * P * m.line.Np, L.stb2},
+      {DGH_QB1, &L.qb1, (size_t)m.Kpnt * 3 * P * P, L.stb1},
   };
   for (const Item& it : items) {
     if (it.n == 0) continue;
-    char* dst = c->ws + it.r->off;
+    char* dst = c->ws + it.r->off + shot * it.stride * sizeof(double);
     if (arr && arr[it.idx]) {
       HIPCHECK(c, hipMemcpy(dst, arr[it.idx], it.n * sizeof(double), hipMemcpyHostToDevice));
     } else {
@@ -764,7 +777,7 @@ dgh_status dgh_set_state(dgh_ctx* c, int shot, const double* const* arr) {
 dgh_status dgh_read_fields(dgh_ctx* c, int shot, double* const* arr) {
   if (!c || !arr) return DGH_EINVAL;
   if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "read before bind");
-  if (shot != 0) return fail(c, DGH_EINVAL, "shot out of range");
+  if (shot < 0 || shot >= c->n_shots) return fail(c, DGH_EINVAL, "shot out of range");
   HIPCHECK(c, hipStreamSynchronize(c->stream));
   const dgh::Mesh& m = c->mesh;
   const Layout& L = c->lay;
@@ -773,33 +786,40 @@ dgh_status dgh_read_fields(dgh_ctx* c, int shot, double* const* arr) {
   for (int which : {DGH_Q3, DGH_RES3}) {
     if (!arr[which]) continue;
     const Region& r = which == DGH_Q3 ? L.q3[cur] : L.res3;
-    HIPCHECK(c, hipMemcpy(buf.data(), c->ws + r.off, r.bytes, hipMemcpyDeviceToHost));
+    HIPCHECK(c, hipMemcpy(buf.data(), c->ws + r.off + shot * L.st3 * sizeof(double),
+                          buf.size() * sizeof(double), hipMemcpyDeviceToHost));
     from_tiles(buf.data(), arr[which], c->slot2elem, Np);
   }
-  struct Item { int idx; const Region* r; size_t n; };
+  struct Item { int idx; const Region* r; size_t n, stride; };
   const Item items[] = {
-      {DGH_Q2, &L.q2[cur], (size_t)m.Ktri * P * 3 * m.tri.Np},
-      {DGH_RES2, &L.res2, (size_t)m.Ktri * P * 3 * m.tri.Np},
-      {DGH_QB3, &L.qb3, (size_t)m.Ktri * m.tri.Np},
-      {DGH_Q03, &L.q03, (size_t)m.Ktri * m.tri.Np},
-      {DGH_Q1, &L.q1[cur], (size_t)m.Klin * P * P * 2 * m.line.Np},
-      {DGH_RES1, &L.res1, (size_t)m.Klin * P * P * 2 * m.line.Np},
-      {DGH_QB2, &L.qb2, (size_t)m.Klin * 2 * P * m.line.Np},
-      {DGH_Q02, &L.q02, (size_t)m.Klin * 2 * P * m.line.Np},
-      {DGH_QB1, &L.qb1, (size_t)m.Kpnt * 3 * P * P},
+      {DGH_Q2, &L.q2[cur], (size_t)m.Ktri * P * 3 * m.tri.Np, L.st2},
+      {DGH_RES2, &L.res2, (size_t)m.Ktri * P * 3 * m.tri.Np, L.st2},
+      {DGH_QB3, &L.qb3, (size_t)m.Ktri * m.tri.Np, L.stb3},
+      {DGH_Q03, &L.q03, (size_t)m.Ktri * m.tri.Np, L.stb3},
+      {DGH_Q1, &L.q1[cur], (size_t)m.Klin * P * P * 2 * m.line.Np, L.st1},
+      {DGH_RES1, &L.res1, (size_t)m.Klin * P * P * 2 * m.line.Np, L.st1},
+      {DGH_QB2, &L.qb2, (size_t)m.Klin * 2 * P * m.line.Np, L.stb2},
+      {DGH_Q02, &L.q02, (size_t)m.Klin * 2 * P * m.line.Np, L.stb2},
+      {DGH_QB1, &L.qb1, (size_t)m.Kpnt * 3 * P * P, L.stb1},
   };
   for (const Item& it : items)
     if (arr[it.idx] && it.n)
-      HIPCHECK(c, hipMemcpy(arr[it.idx], c->ws + it.r->off, it.n * sizeof(double), hipMemcpyDeviceToHost));
+      HIPCHECK(c, hipMemcpy(arr[it.idx], c->ws + it.r->off + shot * it.stride * sizeof(double),
+                            it.n * sizeof(double), hipMemcpyDeviceToHost));
   return DGH_OK;
 }
 
 dgh_status dgh_set_source(dgh_ctx* c, int shot, const double* xs, double f0, double t0, double amp) {
   if (!c || !xs) return DGH_EINVAL;
   if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "set_source before bind");
-  if (shot != 0) return fail(c, DGH_EINVAL, "shot out of range");
+  if (shot < 0 || shot >= c->n_shots) return fail(c, DGH_EINVAL, "shot out of range");
+  if (!std::isfinite(f0) || !std::isfinite(t0) || !std::isfinite(amp))
+    return fail(c, DGH_EINVAL, "source parameters must be finite");
   if (amp == 0.0) {
-    c->src_elem = -1;
+    c->src_slot[shot] = -1;
+    const double par[4] = {-1.0, 0.0, 0.0, 0.0};
+    HIPCHECK(c, hipMemcpy(c->ws + c->lay.srcp.off + (size_t)shot * 4 * sizeof(double), par,
+                          sizeof(par), hipMemcpyHostToDevice));
     return DGH_OK;
   }
   const dgh::Mesh& m = c->mesh;
@@ -829,11 +849,12 @@ dgh_status dgh_set_source(dgh_ctx* c, int shot, const double* xs, double f0, dou
     for (int k = 0; k < Np; ++k) w[a] += m.tet.V[a * Np + k] * psi[k];
     w[a] /= m.J[best];
   }
-  HIPCHECK(c, hipMemcpy(c->ws + c->lay.srcw.off, w.data(), Np * sizeof(double), hipMemcpyHostToDevice));
-  c->src_elem = c->elem2slot[best];
-  c->f0 = f0;
-  c->t0 = t0;
-  c->amp = amp;
+  HIPCHECK(c, hipMemcpy(c->ws + c->lay.srcw.off + (size_t)shot * Np * sizeof(double), w.data(),
+                        Np * sizeof(double), hipMemcpyHostToDevice));
+  c->src_slot[shot] = c->elem2slot[best];
+  const double par[4] = {(double)c->src_slot[shot], f0, t0, amp};
+  HIPCHECK(c, hipMemcpy(c->ws + c->lay.srcp.off + (size_t)shot * 4 * sizeof(double), par,
+                        sizeof(par), hipMemcpyHostToDevice));
   return DGH_OK;
 }
 
@@ -842,16 +863,13 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
   if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "step before bind");
   if (n_steps < 0 || !(dt > 0) || !std::isfinite(t_start)) return fail(c, DGH_EINVAL, "bad step arguments");
   const Layout& L = c->lay;
-  const double* srcw = dptr<double>(c, L.srcw);
+  dgh::Shots sh{c->n_shots, L.st3, L.st2, L.stb3, L.st1, L.stb2, L.stb1,
+                dptr<double>(c, L.srcw), dptr<double>(c, L.srcp), 0.0};
   for (int it = 0; it < n_steps; ++it) {
     const double t = t_start + it * dt;
     for (int s = 0; s < 5; ++s) {
       const int o = c->cur, n = 1 - c->cur;
-      double S = 0.0;
-      if (c->src_elem >= 0) {
-        const double tau = t + kC[s] * dt - c->t0;
-        S = c->amp * tau * std::exp(-(M_PI * c->f0 * tau) * (M_PI * c->f0 * tau));
-      }
+      sh.tau = t + kC[s] * dt;
       if (c->timing) {
         if (c->ev_used + 2 > c->ev.size()) {
           for (int k = 0; k < 64; ++k) {
@@ -864,7 +882,7 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
       }
       HIPCHECK(c, dgh::launch_level3(c->L3, dptr<double>(c, L.q3[o]), dptr<double>(c, L.q3[n]),
                                      dptr<double>(c, L.res3), dptr<double>(c, L.qb3), kA[s], kB[s],
-                                     dt, c->src_elem, srcw, S, c->stream));
+                                     dt, sh, c->stream));
       if (c->timing) {
         HIPCHECK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
@@ -875,7 +893,7 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
                                        dptr<double>(c, L.q03), dptr<double>(c, L.q3[n]),
                                        dptr<double>(c, L.q1[o]), dptr<double>(c, L.q1[n]),
                                        dptr<double>(c, L.res1), dptr<double>(c, L.qb1),
-                                       dptr<double>(c, L.q02), kA[s], kB[s], dt, c->stream));
+                                       dptr<double>(c, L.q02), kA[s], kB[s], dt, sh, c->stream));
       c->cur = n;
     }
   }
@@ -885,9 +903,10 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
 dgh_status dgh_energy(dgh_ctx* c, int shot, double* e) {
   if (!c || !e) return DGH_EINVAL;
   if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "energy before bind");
-  if (shot != 0) return fail(c, DGH_EINVAL, "shot out of range");
+  if (shot < 0 || shot >= c->n_shots) return fail(c, DGH_EINVAL, "shot out of range");
   const Layout& L = c->lay;
-  HIPCHECK(c, dgh::launch_energy(c->L3, dptr<double>(c, L.q3[c->cur]), dptr<double>(c, L.mass3),
+  HIPCHECK(c, dgh::launch_energy(c->L3, dptr<double>(c, L.q3[c->cur]) + shot * L.st3,
+                                 dptr<double>(c, L.mass3),
                                  dptr<double>(c, L.J3), dptr<double>(c, L.esum), c->stream));
   std::vector<double> part(c->ntile);
   HIPCHECK(c, hipMemcpyAsync(part.data(), c->ws + L.esum.off, c->ntile * sizeof(double),
@@ -902,7 +921,7 @@ dgh_status dgh_energy(dgh_ctx* c, int shot, double* e) {
 dgh_status dgh_check(dgh_ctx* c, int shot, double e_ref, double rel_tol, double* e_out) {
   if (!c) return DGH_EINVAL;
   if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "check before bind");
-  if (shot != 0) return fail(c, DGH_EINVAL, "shot out of range");
+  if (shot < 0 || shot >= c->n_shots) return fail(c, DGH_EINVAL, "shot out of range");
   if (!(rel_tol >= 0.0)) return fail(c, DGH_EINVAL, "rel_tol must be >= 0");
   const dgh::Mesh& m = c->mesh;
   const Layout& L = c->lay;
@@ -910,6 +929,8 @@ dgh_status dgh_check(dgh_ctx* c, int shot, double e_ref, double rel_tol, double*
   const size_t n3 = (size_t)c->ntile * 4 * Np * dgh::kTile;
   const Region* regs[] = {&L.q3[cur], &L.res3, &L.q2[cur], &L.res2, &L.qb3, &L.q03,
                           &L.q1[cur], &L.res1, &L.qb2, &L.q02, &L.qb1};
+  const size_t strides[] = {L.st3, L.st3, L.st2, L.st2, L.stb3, L.stb3,
+                            L.st1, L.st1, L.stb2, L.stb2, L.stb1};
   const size_t ns[] = {n3, n3,
                        (size_t)m.Ktri * P * 3 * m.tri.Np, (size_t)m.Ktri * P * 3 * m.tri.Np,
                        (size_t)m.Ktri * m.tri.Np, (size_t)m.Ktri * m.tri.Np,
@@ -920,7 +941,7 @@ dgh_status dgh_check(dgh_ctx* c, int shot, double e_ref, double rel_tol, double*
   dgh::ScanList sl{};
   for (int a = 0; a < DGH_NARRAYS; ++a)
     if (ns[a] > 0) {
-      sl.ptr[sl.count] = dptr<double>(c, *regs[a]);
+      sl.ptr[sl.count] = dptr<double>(c, *regs[a]) + shot * strides[a];
       sl.n[sl.count] = ns[a];
       ++sl.count;
     }

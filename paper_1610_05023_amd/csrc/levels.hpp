@@ -83,9 +83,26 @@ struct Lvl0 {
   const double* Tt;    // transposed corner map: Tt[k][row] = T[row][k], 3P^2 x 3P^2
 };
 
+// Shots stepped together: every state array holds n shots, shot k of an
+// array at k times its stride (in doubles).  Point sources per shot: w[k][Np]
+// weights, par[k][4] = (slot of the element or -1, f0, t0, amp); tau = the
+// stage time.
+struct Shots {
+  int n;
+  size_t st3;    // q3, res3
+  size_t st2;    // q2, res2
+  size_t stb3;   // qb3, q0_3
+  size_t st1;    // q1, res1
+  size_t stb2;   // qb2, q0_2
+  size_t stb1;   // qb1
+  const double* srcw;
+  const double* srcp;
+  double tau;
+};
+
 hipError_t launch_level3(const Lvl3& L, const double* qo, double* qn, double* res,
-                         const double* qb3, double A, double B, double dt, int src_e,
-                         const double* src_w, double src_s, hipStream_t st);
+                         const double* qb3, double A, double B, double dt, const Shots& sh,
+                         hipStream_t st);
 // Work list of the merged boundary kernel: block b updates the triangles
 // tris[b][*], then the lines lines[b][*] (each with its edge system), then
 // the corners corners[b][*]; -1 ends a list.  Blocks with lines hold every
@@ -103,7 +120,8 @@ hipError_t launch_boundary(const LvlB& W, const Lvl2& L2, const Lvl1& L1, const 
                            const Lvl3& L3, const double* q2o, double* q2n, double* res2,
                            double* qb2, double* qb3, double* q03, const double* q3n,
                            const double* q1o, double* q1n, double* res1, double* qb1,
-                           double* q02, double A, double B, double dt, hipStream_t st);
+                           double* q02, double A, double B, double dt, const Shots& sh,
+                           hipStream_t st);
 // Arrays scanned by the finiteness check (at most kScanMax of them); the
 // kernel writes one int per (array, block): 1 if a non-finite value was seen.
 constexpr int kScanMax = 12;

@@ -76,8 +76,7 @@ template <int N>
 __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double* __restrict__ qo,
                                                    double* __restrict__ qn, double* __restrict__ res,
                                                    const double* __restrict__ qb3, double A, double B,
-                                                   double dt, int src_e,
-                                                   const double* __restrict__ src_w, double src_s) {
+                                                   double dt, Shots sh) {
   using D = Dims3<N>;
   constexpr int Np = D::Np, Nfp = D::Nfp, RG = D::RG, FK = D::FK;
   constexpr unsigned FS = Np * kTile * 8;   // bytes between two fields of a tile
@@ -94,8 +93,15 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
     for (int i = threadIdx.x; i < D::NFRAG * 16; i += blockDim.x) sops[i] = L.ops[i];
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int tile = xcd_block(blockIdx.x, gridDim.x) * kWaves3 + (threadIdx.x >> 6);
+  // (block, shot) pairs are dealt to the XCDs in contiguous ranges
+  const int lin = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int shot = lin / gridDim.x;
+  const int tile = (lin - shot * gridDim.x) * kWaves3 + (threadIdx.x >> 6);
   if (tile >= L.ntile) return;
+  qo += shot * sh.st3;
+  qn += shot * sh.st3;
+  res += shot * sh.st3;
+  qb3 += shot * sh.stb3;
   const int es = lane & 15, g = lane >> 4;
   const int ta = (lane & 3) + 4 * g;   // this lane's entry of a 16-value A fragment
   const double* frag = (D::kLds ? sops : L.ops) + ta;
@@ -262,7 +268,12 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
   // loads at clamped rows, stores masked
   {
     const bool live = irho != 0.0;
-    const bool src = e == src_e;
+    // point source S(tau) = amp (tau - t0) exp(-pi^2 f0^2 (tau - t0)^2)
+    const double* sp = sh.srcp + 4 * shot;
+    const bool src = (double)e == sp[0];
+    const double tr = sh.tau - sp[2], ar = M_PI * sp[1] * tr;
+    const double src_s = sp[3] * tr * exp(-ar * ar);
+    const double* src_w = sh.srcw + (size_t)shot * Np;
     constexpr int EC = 3;
 #pragma unroll
     for (int i0 = 0; i0 < RG; i0 += EC) {
@@ -335,8 +346,7 @@ __global__ void k_energy(Lvl3 L, const double* __restrict__ q, const double* __r
 
 template <int N>
 hipError_t launch3(const Lvl3& L, const double* qo, double* qn, double* res, const double* qb3,
-                   double A, double B, double dt, int src_e, const double* src_w, double src_s,
-                   hipStream_t st) {
+                   double A, double B, double dt, const Shots& sh, hipStream_t st) {
   using D = Dims3<N>;
   constexpr int Nfp = D::Nfp;
   const size_t lds = sizeof(double) * ((4 * Nfp + 96 * Nfp + 1) / 2 + (D::kLds ? D::NFRAG * 16 : 0));
@@ -347,23 +357,24 @@ hipError_t launch3(const Lvl3& L, const double* qo, double* qn, double* res, con
     attr = true;
   }
   const int blocks = (L.ntile + kWaves3 - 1) / kWaves3;
-  hipLaunchKernelGGL(k_level3<N>, dim3(blocks), dim3(kWaves3 * 64), lds, st, L, qo, qn, res, qb3, A, B,
-                     dt, src_e, src_w, src_s);
+  if (sh.n < 1 || (long long)blocks * sh.n > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_level3<N>, dim3(blocks, sh.n), dim3(kWaves3 * 64), lds, st, L, qo, qn, res,
+                     qb3, A, B, dt, sh);
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_level3(const Lvl3& L, const double* qo, double* qn, double* res,
-                         const double* qb3, double A, double B, double dt, int src_e,
-                         const double* src_w, double src_s, hipStream_t st) {
+                         const double* qb3, double A, double B, double dt, const Shots& sh,
+                         hipStream_t st) {
   switch (L.N) {
-    case 1: return launch3<1>(L, qo, qn, res, qb3, A, B, dt, src_e, src_w, src_s, st);
-    case 2: return launch3<2>(L, qo, qn, res, qb3, A, B, dt, src_e, src_w, src_s, st);
-    case 3: return launch3<3>(L, qo, qn, res, qb3, A, B, dt, src_e, src_w, src_s, st);
-    case 4: return launch3<4>(L, qo, qn, res, qb3, A, B, dt, src_e, src_w, src_s, st);
-    case 5: return launch3<5>(L, qo, qn, res, qb3, A, B, dt, src_e, src_w, src_s, st);
-    case 6: return launch3<6>(L, qo, qn, res, qb3, A, B, dt, src_e, src_w, src_s, st);
+    case 1: return launch3<1>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    case 2: return launch3<2>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    case 3: return launch3<3>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    case 4: return launch3<4>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    case 5: return launch3<5>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    case 6: return launch3<6>(L, qo, qn, res, qb3, A, B, dt, sh, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -73,3 +73,19 @@ def test_errors_reported():
         s.step(1, 1e-3)                                       # before bind
     with pytest.raises(DghError, match="ENOMEM"):
         s._call("dgh_bind_workspace", None, 16, None)         # workspace too small
+
+
+def test_shot_count_and_workspace():
+    """n_shots is range-checked at creation; the workspace grows with the
+    number of shots by the per-shot state (the shared constants stay)."""
+    from paper_1610_05023_amd import Solver, DghError
+    VX, E = w.kuhn_mesh(3)
+    K = E.shape[0]
+    for bad in (0, 4097):
+        with pytest.raises(DghError, match="dgh_create"):
+            Solver(VX, E, 2, 2, np.ones(K), np.ones(K), n_shots=bad)
+    sizes = [Solver(VX, E, 2, 2, np.ones(K), np.ones(K), n_shots=k).workspace_size()
+             for k in (1, 2, 5)]
+    assert sizes[1] > sizes[0] and abs((sizes[2] - sizes[1]) - 3 * (sizes[1] - sizes[0])) < 4096
+    s = Solver(VX, E, 2, 2, np.ones(K), np.ones(K), n_shots=2)
+    assert s.counts["n_shots"] == 2
