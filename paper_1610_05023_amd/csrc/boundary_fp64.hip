@@ -1,14 +1,12 @@
-// FP64 boundary levels of one Runge-Kutta stage in one launch (Algorithm 1
-// after the volume update): the 2D face systems with the face rule, the 1D
-// edge systems with the edge compatibility systems, and the corner systems.
+// FP64 edge and corner levels of one Runge-Kutta stage (Algorithm 1 after
+// the volume and face updates): the 1D edge systems with the edge
+// compatibility systems, and the corner systems.
 //
-// Every block works from its entry in the work list: first its triangles
-// (P sets in parallel: thread = triangle x set x node), then its lines one
-// after the other, then its corners.  A block that owns a line also owns the
-// triangles next to it and, if the line ends at a corner, the corner's three
-// lines, so the new 2D traces the edge system needs and the new 1D traces
-// the corner system needs are produced by the same block.  Blocks without
-// lines (most of them) only update triangles.
+// Every block works on one line group of the work list: its lines one
+// after the other, then its corners.  A group holds the three lines of each
+// of its corners, so the new 1D traces a corner system needs are produced
+// by the same block; the new 2D traces the edge systems need come from the
+// face kernel launched before.
 //
 // Discretisation as for the volume (Section 3.2), with the face system
 //   (1+g_i) dp*_i/dt + rho c^2 div v_i = 0, rho dv_i/dt + grad p_i = 0,
@@ -60,6 +58,8 @@ struct Bufs {
   double *q1n, *res1, *qb1, *q02;
 };
 
+// One block per line group: its lines, then its corners.  NPT edge nodes
+// per thread (NPT 512 >= P^2 Np1).
 template <int NPT>
 __global__ void __launch_bounds__(512, 4) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0 L0, int np3,
                                                      Bufs b, Shots sh, double A, double B,
@@ -81,159 +81,11 @@ __global__ void __launch_bounds__(512, 4) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, L
     b.q02 += k * sh.stb2;
     b.qb1 += k * sh.stb1;
   }
-  const int P = L2.P, Pe = P > 0 ? P : 1;
+  const int P = L2.P;
   const int tid = threadIdx.x, nth = blockDim.x, blk = blockIdx.x;
   // Every phase issues all of a thread's global loads before its first
   // global store, so that they are in flight together (the state arrays may
   // alias as far as the compiler knows); small constant tables sit in LDS.
-  // ---------------------------------------------------------------- 2D ----
-  {
-    const int Np = L2.Np, Nfp = L2.Nfp, NE = 3 * Nfp, NS = W.NS, TPB = W.TPB;
-    double* sDr = smem;
-    double* sDs = sDr + Np * Np;
-    double* sL = sDs + Np * Np;                 // Np x NE
-    double* sg = sL + Np * NE;                  // P: gamma
-    double* sq = sg + Pe;                       // TPB x P x 3 x Np
-    double* sf = sq + TPB * P * 3 * Np;         // TPB x P x 2 x NE
-    double* sps = sf + TPB * P * 2 * NE;        // TPB x P x Np
-    double* sS = sps + TPB * P * Np;            // TPB x Np
-    for (int x = tid; x < 2 * Np * Np + Np * NE; x += nth) sDr[x] = L2.ops[x];
-    for (int x = tid; x < P; x += nth) sg[x] = L2.gamma[x];
-    const int per = Pe * NS;
-    const int tl = tid / per, rem = tid - tl * per, i = rem / NS, slot = rem - i * NS;
-    const int ntri = W.ntri[blk];
-    for (int c0 = 0; c0 < ntri; c0 += TPB) {
-      const int t = (tl < TPB && c0 + tl < ntri) ? W.tris[blk * W.maxtri + c0 + tl] : -1;
-      __syncthreads();
-      if (t >= 0)
-        for (int x = rem; x < P * 3 * Np; x += per)
-          sq[tl * P * 3 * Np + x] = b.q2o[(size_t)t * P * 3 * Np + x];
-      double rx = 0, ry = 0, sx = 0, sy = 0, irho = 0, Kb = 0, Z = 1;
-      int info[6] = {0, 0, 0, 0, 0, 0};
-      if (t >= 0) {
-        const double* gg = L2.geo + (size_t)t * 8;
-        rx = gg[0]; ry = gg[1]; sx = gg[2]; sy = gg[3]; irho = gg[4]; Kb = gg[5]; Z = gg[6];
-        for (int k = 0; k < 6; ++k) info[k] = L2.info[t * 8 + k];
-      }
-      const bool act = t >= 0 && i < P;
-      // the previous residual and q0 of this thread's node, the new 3D trace
-      // for the face rule, and the exterior values of its edge node
-      double r0 = 0, r1 = 0, r2 = 0, S0 = 0, p3 = 0, u3 = 0;
-      if (act && slot < Np) {
-        const size_t base = ((size_t)t * P + i) * 3 * Np + slot;
-        r0 = b.res2[base];
-        r1 = b.res2[base + Np];
-        r2 = b.res2[base + 2 * Np];
-        S0 = b.q03[(size_t)t * Np + slot];
-      }
-      if (t >= 0 && i == 0 && slot < Np) {
-        const int e = info[0], n3 = L2.tetnode[(size_t)t * Np + slot];
-        const double* q3 = b.q3n + (size_t)(e >> 4) * 4 * np3 * kTile + (e & 15);
-        p3 = q3[n3 * kTile];
-        u3 = q3[((1 + info[1]) * np3 + n3) * kTile];
-      }
-      int ef = 0, ek = 0, code = 0, nn = 0, fa = 0;
-      double gP = 0, gA = 0, gB = 0, gZ = 1, grm = 0;
-      if (act && slot < NE) {
-        ef = slot / Nfp;
-        ek = slot - ef * Nfp;
-        code = info[3 + ef];
-        nn = L2.nbrnode[(t * 3 + ef) * Nfp + ek];
-        fa = L2.fmask[ef * Nfp + ek];
-        if (code >= 0) {
-          const double* q = b.q2o + ((size_t)code * P + i) * 3 * Np;
-          gP = q[nn];
-          gA = q[Np + nn];
-          gB = q[2 * Np + nn];
-          gZ = L2.geo[(size_t)code * 8 + 6];
-        } else {
-          const int c = -1 - code;
-          if ((c & 3) == 0) grm = b.qb2[(((size_t)(c >> 3) * 2 + ((c >> 2) & 1)) * P + i) * Nfp + nn];
-        }
-      }
-      __syncthreads();
-      const double* sqt = sq + (tl * P + i) * 3 * Np;
-      // edge normals (a, b) of the edges s = -1, r + s = 0, r = -1 and Fscale
-      double en[3][3];
-      {
-        const double v[3][2] = {{-sx, -sy}, {rx + sx, ry + sy}, {-rx, -ry}};
-        for (int f = 0; f < 3; ++f) {
-          const double m = sqrt(v[f][0] * v[f][0] + v[f][1] * v[f][1]);
-          en[f][2] = m;
-          en[f][0] = t >= 0 ? v[f][0] / m : 0.0;
-          en[f][1] = t >= 0 ? v[f][1] / m : 0.0;
-        }
-      }
-      const double Ki = act ? Kb / (1.0 + sg[i]) : 0.0;
-      // ---- fluxes on the 3 edges
-      if (act && slot < NE) {
-        const double na = en[ef][0], nb = en[ef][1];
-        const double pM = sqt[fa];
-        const double vnM = na * sqt[Np + fa] + nb * sqt[2 * Np + fa];
-        double pF, vnF;
-        if (code >= 0)
-          upwind2(pM, vnM, Z, gP, na * gA + nb * gB, gZ, pF, vnF);
-        else
-          bcflux2((-1 - code) & 3, pM, vnM, Z, grm, pF, vnF);
-        double* sft = sf + (tl * P + i) * 2 * NE;
-        sft[slot] = en[ef][2] * Ki * (vnM - vnF);
-        sft[NE + slot] = en[ef][2] * irho * (pM - pF);
-      }
-      __syncthreads();
-      // ---- volume, lift, update of set i
-      if (act && slot < Np) {
-        const int a = slot;
-        const double* sft = sf + (tl * P + i) * 2 * NE;
-        double pr_ = 0, ps_ = 0, div = 0;
-        for (int m = 0; m < Np; ++m) {
-          const double dr = sDr[a * Np + m], ds = sDs[a * Np + m];
-          const double p = sqt[m], va = sqt[Np + m], vb = sqt[2 * Np + m];
-          pr_ += dr * p;
-          ps_ += ds * p;
-          div += dr * (rx * va + ry * vb) + ds * (sx * va + sy * vb);
-        }
-        double lp = 0, lv[3] = {0, 0, 0};
-        for (int f = 0; f < 3; ++f)
-          for (int k = 0; k < Nfp; ++k) {
-            const int j = f * Nfp + k;
-            const double l = sL[a * NE + j];
-            lp += l * sft[j];
-            lv[f] += l * sft[NE + j];
-          }
-        double rhs1 = -irho * (rx * pr_ + sx * ps_), rhs2 = -irho * (ry * pr_ + sy * ps_);
-        for (int f = 0; f < 3; ++f) {
-          rhs1 += en[f][0] * lv[f];
-          rhs2 += en[f][1] * lv[f];
-        }
-        const size_t base = ((size_t)t * P + i) * 3 * Np + a;
-        r0 = A * r0 + dt * (-Ki * div + lp);
-        r1 = A * r1 + dt * rhs1;
-        r2 = A * r2 + dt * rhs2;
-        b.res2[base] = r0;
-        b.res2[base + Np] = r1;
-        b.res2[base + 2 * Np] = r2;
-        sps[(tl * P + i) * Np + a] = sqt[a] - S0 + B * r0;
-        b.q2n[base + Np] = sqt[Np + a] + B * r1;
-        b.q2n[base + 2 * Np] = sqt[2 * Np + a] + B * r2;
-      }
-      __syncthreads();
-      // ---- face rule: r+ from the new 3D trace, r- = (1/M) sum g_i p*_i
-      if (t >= 0 && i == 0 && slot < Np) {
-        const int a = slot;
-        const double rp = 0.5 * (p3 + Z * (double)info[2] * u3);
-        double rm = 0.0;
-        for (int s = 0; s < P; ++s) rm += sg[s] * sps[(tl * P + s) * Np + a];
-        rm *= L2.invM;
-        const double S = rp + rm;
-        b.qb3[(size_t)t * Np + a] = rm;
-        b.q03[(size_t)t * Np + a] = S;
-        sS[tl * Np + a] = S;
-      }
-      __syncthreads();
-      if (act && slot < Np)
-        b.q2n[((size_t)t * P + i) * 3 * Np + slot] = sps[(tl * P + i) * Np + slot] + sS[tl * Np + slot];
-    }
-  }
   if (W.maxlin == 0 || W.lines[blk * W.maxlin] < 0 || P == 0) return;
   // ---------------------------------------------------------------- 1D ----
   const int PP = P * P, Np = L1.Np, n2 = 2 * P, n3 = 3 * PP, mc = W.maxcor;
@@ -254,7 +106,6 @@ __global__ void __launch_bounds__(512, 4) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, L
   double* srp0 = sC + mc * 3 * PP * 2; // 3 PP
   double* sred = srp0 + n3;            // nth partial sums of the corner systems
   int* cInfo = reinterpret_cast<int*>(sred + nth);   // maxcor x 3: line << 1 | end
-  __syncthreads();   // the 2D phase is done with its LDS
   for (int x = tid; x < Np * Np + 2 * Np; x += nth) cDr[x] = L1.ops[x];
   for (int x = tid; x < n2 * n2; x += nth) {
     cG[x] = L1.G[x];
@@ -439,6 +290,21 @@ __global__ void __launch_bounds__(512, 4) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, L
 
 }  // namespace
 
+// Raises the dynamic LDS limit of a kernel when a launch needs more.
+hipError_t set_lds(const void* fn, size_t bytes) {
+  static const void* fns[8] = {};
+  static size_t have[8] = {};
+  for (int i = 0; i < 8; ++i) {
+    if (fns[i] == fn && bytes <= have[i]) return hipSuccess;
+    if (fns[i] == fn || !fns[i]) {
+      fns[i] = fn;
+      have[i] = bytes;
+      return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    }
+  }
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 hipError_t launch_boundary(const LvlB& W, const Lvl2& L2, const Lvl1& L1, const Lvl0& L0,
                            const Lvl3& L3, const double* q2o, double* q2n, double* res2,
                            double* qb2, double* qb3, double* q03, const double* q3n,
@@ -447,35 +313,26 @@ hipError_t launch_boundary(const LvlB& W, const Lvl2& L2, const Lvl1& L1, const 
                            hipStream_t st) {
   if (W.nblocks == 0) return hipSuccess;
   if (sh.n < 1 || sh.n > 65535) return hipErrorInvalidValue;
-  const int P = L2.P, Np2 = L2.Np, NE = 3 * L2.Nfp, TPB = W.TPB, Np1 = L1.Np, PP = P * P;
-  const int Pe = P > 0 ? P : 1, n2 = 2 * P, n3 = 3 * PP;
-  const size_t a2 = 2 * Np2 * Np2 + Np2 * NE + Pe + TPB * P * 3 * Np2 + TPB * P * 2 * NE +
-                    TPB * P * Np2 + TPB * Np2;
+  const int P = L2.P, Np1 = L1.Np, PP = P * P;
+  if (P == 0) return hipSuccess;   // no edge or corner systems
+  const int n2 = 2 * P, n3 = 3 * PP;
   const size_t a1 = Np1 * Np1 + 2 * Np1 + 2 * n2 * n2 + 2 * PP + P + PP * 2 * Np1 +
                     2 * PP * Np1 + 3 * n2 * Np1 + W.maxcor * 3 * PP * 2 + n3 + 512 +
                     (W.maxcor * 3 + 1) / 2 + 1;
-  const size_t lds = sizeof(double) * (a2 > a1 ? a2 : a1);
   Bufs b{q2o, q2n, res2, qb2, qb3, q03, q3n, q1o, q1n, res1, qb1, q02};
+  if (PP * Np1 > 1024) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * a1;
   // one edge node per thread unless P^2 Np1 exceeds the block (P > 10)
   if (PP * Np1 <= 512) {
-    static size_t attr = 0;
-    if (lds > attr) {
-      (void)hipFuncSetAttribute((const void*)k_boundary<1>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      attr = lds;
-    }
-    hipLaunchKernelGGL(k_boundary<1>, dim3(W.nblocks, sh.n), dim3(512), lds, st, W, L2, L1, L0, L3.Np,
-                       b, sh, A, B, dt);
+    hipError_t e = set_lds((const void*)k_boundary<1>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_boundary<1>, dim3(W.nblocks, sh.n), dim3(512), lds, st, W, L2, L1, L0,
+                       L3.Np, b, sh, A, B, dt);
   } else {
-    if (PP * Np1 > 1024) return hipErrorInvalidValue;
-    static size_t attr = 0;
-    if (lds > attr) {
-      (void)hipFuncSetAttribute((const void*)k_boundary<2>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      attr = lds;
-    }
-    hipLaunchKernelGGL(k_boundary<2>, dim3(W.nblocks, sh.n), dim3(512), lds, st, W, L2, L1, L0, L3.Np,
-                       b, sh, A, B, dt);
+    hipError_t e = set_lds((const void*)k_boundary<2>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_boundary<2>, dim3(W.nblocks, sh.n), dim3(512), lds, st, W, L2, L1, L0,
+                       L3.Np, b, sh, A, B, dt);
   }
   return hipGetLastError();
 }

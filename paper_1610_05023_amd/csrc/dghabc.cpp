@@ -37,7 +37,7 @@ struct Layout {
   Region q3[2], res3, geo3, zn3, nbr3, ops3, fmask3, fmap3, mass3, J3, esum;
   Region q2[2], res2, qb3, q03, geo2, info2, tetnode2, nbrnode2, ops2, fmask2, gamma;
   Region q1[2], res1, qb2, q02, geo1, info1, trinode1, ops1, cji, cij, G, H;
-  Region qb1, info0, nrm0, T, srcw, srcp, wntri, wtris, wlines, wcorners, flags;
+  Region qb1, info0, nrm0, T, srcw, srcp, wlines, wcorners, flags, ops2f;
   // per-shot strides (doubles) of the state arrays
   size_t st3 = 0, st2 = 0, stb3 = 0, st1 = 0, stb2 = 0, stb1 = 0;
   Region* add(Region& r, size_t bytes) {
@@ -79,7 +79,8 @@ struct dgh_ctx {
   dgh::Lvl1 L1{};
   dgh::Lvl0 L0{};
   dgh::LvlB LB{};
-  std::vector<int> wntri, wtris, wlines, wcorners;  // boundary work list (host copy)
+  std::vector<int> wlines, wcorners;  // line-group work list (host copy)
+  dgh::LvlF LF{};
 };
 
 namespace {
@@ -106,7 +107,7 @@ T* dptr(dgh_ctx* c, const Region& r) {
 
 // Builds the device-layout arrays on the host.
 struct HostArrays {
-  std::vector<double> geo3, zn3, ops3, mass3, J3;
+  std::vector<double> geo3, zn3, ops3, mass3, J3, ops2f;
   std::vector<int> nbr3, fmask3, fmap3;
   std::vector<double> geo2, ops2;
   std::vector<int> info2, tetnode2, nbrnode2, fmask2;
@@ -117,15 +118,12 @@ struct HostArrays {
   bool map_ok = true;
 };
 
-// Groups lines that must be updated by one block: the three lines of a
-// corner, and lines sharing a triangle; each group also takes the triangles
-// next to its lines.  The remaining triangles are dealt in chunks of TPB.
+// Groups the lines that must be updated by one block: lines joined through
+// a corner, so that the corner system sees the new traces of its three
+// lines.  Corner groups come first (they carry the longest chains).
 void build_worklist(dgh_ctx* c) {
   const dgh::Mesh& m = c->mesh;
-  const int P = c->P, Pe = P > 0 ? P : 1;
-  const int NS = std::max(m.tri.Np, 3 * m.tri.Nfp);
-  const int TPB = std::max(1, 512 / (Pe * NS));
-  const int Kl = m.Klin, Kt = m.Ktri;
+  const int Kl = m.Klin;
   std::vector<int> parent(Kl);
   for (int l = 0; l < Kl; ++l) parent[l] = l;
   auto find = [&](int x) {
@@ -137,68 +135,38 @@ void build_worklist(dgh_ctx* c) {
     unite(m.pnt_line[3 * p], m.pnt_line[3 * p + 1]);
     unite(m.pnt_line[3 * p], m.pnt_line[3 * p + 2]);
   }
-  std::vector<int> tri_line(Kt, -1);
-  for (int l = 0; l < Kl; ++l)
-    for (int side = 0; side < 2; ++side) {
-      const int t = m.lin_tri[2 * l + side];
-      if (tri_line[t] >= 0) unite(tri_line[t], l);
-      tri_line[t] = l;
-    }
-  std::vector<std::vector<int>> glines, gtris, gcors;
+  std::vector<std::vector<int>> glines, gcors;
   std::vector<int> gid(Kl, -1);
   for (int l = 0; l < Kl; ++l) {
     const int r = find(l);
     if (gid[r] < 0) {
       gid[r] = (int)glines.size();
       glines.emplace_back();
-      gtris.emplace_back();
       gcors.emplace_back();
     }
     glines[gid[r]].push_back(l);
   }
-  std::vector<char> tri_taken(Kt, 0);
-  for (size_t g = 0; g < glines.size(); ++g)
-    for (int l : glines[g])
-      for (int side = 0; side < 2; ++side) {
-        const int t = m.lin_tri[2 * l + side];
-        if (!tri_taken[t]) {
-          tri_taken[t] = 1;
-          gtris[g].push_back(t);
-        }
-      }
   for (int p = 0; p < m.Kpnt; ++p) gcors[gid[find(m.pnt_line[3 * p])]].push_back(p);
-  int maxtri = TPB, maxlin = 0, maxcor = 0;
+  std::vector<int> order(glines.size());
+  for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return glines[a].size() > glines[b].size(); });
+  int maxlin = 0, maxcor = 0;
   for (size_t g = 0; g < glines.size(); ++g) {
-    maxtri = std::max(maxtri, (int)gtris[g].size());
     maxlin = std::max(maxlin, (int)glines[g].size());
     maxcor = std::max(maxcor, (int)gcors[g].size());
   }
-  std::vector<int> rest;
-  for (int t = 0; t < Kt; ++t)
-    if (!tri_taken[t]) rest.push_back(t);
-  const int nface = ((int)rest.size() + TPB - 1) / TPB;
-  const int nb = (int)glines.size() + nface;
+  const int nb = (int)glines.size();
   const int ml = std::max(1, maxlin), mc = std::max(1, maxcor);
-  c->wntri.assign((size_t)std::max(1, nb), 0);
-  c->wtris.assign((size_t)nb * maxtri, -1);
-  c->wlines.assign((size_t)nb * ml, -1);
-  c->wcorners.assign((size_t)nb * mc, -1);
-  for (size_t g = 0; g < glines.size(); ++g) {
-    for (size_t k = 0; k < gtris[g].size(); ++k) c->wtris[g * maxtri + k] = gtris[g][k];
-    c->wntri[g] = (int)gtris[g].size();
-    for (size_t k = 0; k < glines[g].size(); ++k) c->wlines[g * ml + k] = glines[g][k];
-    for (size_t k = 0; k < gcors[g].size(); ++k) c->wcorners[g * mc + k] = gcors[g][k];
+  c->wlines.assign((size_t)std::max(1, nb) * ml, -1);
+  c->wcorners.assign((size_t)std::max(1, nb) * mc, -1);
+  for (int k = 0; k < nb; ++k) {
+    const int g = order[k];
+    for (size_t j = 0; j < glines[g].size(); ++j) c->wlines[(size_t)k * ml + j] = glines[g][j];
+    for (size_t j = 0; j < gcors[g].size(); ++j) c->wcorners[(size_t)k * mc + j] = gcors[g][j];
   }
-  for (int f = 0; f < nface; ++f)
-    for (int k = 0; k < TPB && f * TPB + k < (int)rest.size(); ++k) {
-      c->wtris[((size_t)glines.size() + f) * maxtri + k] = rest[f * TPB + k];
-      c->wntri[glines.size() + f] = k + 1;
-    }
   dgh::LvlB& W = c->LB;
-  W.nblocks = Kt > 0 ? nb : 0;
-  W.TPB = TPB;
-  W.NS = NS;
-  W.maxtri = maxtri;
+  W.nblocks = nb;
   W.maxlin = maxlin;
   W.maxcor = maxcor;
 }
@@ -327,6 +295,30 @@ void build_host_arrays(dgh_ctx* c, HostArrays& h) {
       h.info2[t * 8 + 3 + f] = code;
     }
   }
+  {
+    // MFMA A-fragments of the face kernel (see LvlF::ops)
+    const int RG = (Np2 + 3) / 4, EK = (Nfp2 + 3) / 4;
+    h.ops2f.assign(dgh::frag2_size(m.N), 0.0);
+    const dgh::Mat* Ds[2] = {&m.tri.Dr, &m.tri.Ds};
+    for (int d = 0; d < 2; ++d)
+      for (int rg = 0; rg < RG; ++rg)
+        for (int ks = 0; ks < RG; ++ks)
+          for (int t = 0; t < 16; ++t) {
+            const int row = 4 * rg + (t & 3), col = 4 * ks + (t >> 2);
+            if (row < Np2 && col < Np2)
+              h.ops2f[(((size_t)d * RG + rg) * RG + ks) * 16 + t] = (*Ds[d])[row * Np2 + col];
+          }
+    const size_t off = (size_t)2 * RG * RG * 16;
+    for (int rg = 0; rg < RG; ++rg)
+      for (int e = 0; e < 3; ++e)
+        for (int jj = 0; jj < EK; ++jj)
+          for (int t = 0; t < 16; ++t) {
+            const int row = 4 * rg + (t & 3), k = 4 * jj + (t >> 2);
+            if (row < Np2 && k < Nfp2)
+              h.ops2f[off + (((size_t)rg * 3 + e) * EK + jj) * 16 + t] =
+                  m.tri.LIFT[row * 3 * Nfp2 + e * Nfp2 + k];
+          }
+  }
   h.ops2.clear();
   h.ops2.insert(h.ops2.end(), m.tri.Dr.begin(), m.tri.Dr.end());
   h.ops2.insert(h.ops2.end(), m.tri.Ds.begin(), m.tri.Ds.end());
@@ -444,11 +436,10 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.srcw, S * Np * d);
   L.add(L.srcp, S * 4 * d);
   build_worklist(c);
-  L.add(L.wntri, std::max<size_t>(1, c->wntri.size()) * i4);
-  L.add(L.wtris, std::max<size_t>(1, c->wtris.size()) * i4);
   L.add(L.wlines, std::max<size_t>(1, c->wlines.size()) * i4);
   L.add(L.wcorners, std::max<size_t>(1, c->wcorners.size()) * i4);
   L.add(L.flags, (size_t)dgh::kScanMax * dgh::kScanBlocks * i4);
+  L.add(L.ops2f, (size_t)dgh::frag2_size(m.N) * d);
 }
 
 template <class V>
@@ -508,8 +499,8 @@ void fill_levels(dgh_ctx* c) {
   z.info = dptr<int>(c, L.info0);
   z.nrm = dptr<double>(c, L.nrm0);
   z.Tt = dptr<double>(c, L.T);
-  c->LB.ntri = dptr<int>(c, L.wntri);
-  c->LB.tris = dptr<int>(c, L.wtris);
+  c->LF.np3 = m.tet.Np;
+  c->LF.ops = dptr<double>(c, L.ops2f);
   c->LB.lines = dptr<int>(c, L.wlines);
   c->LB.corners = dptr<int>(c, L.wcorners);
 }
@@ -715,10 +706,9 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
       for (int k = 0; k < n3; ++k) Tt[(size_t)k * n3 + r] = c->habc.T[(size_t)r * n3 + k];
     HIPCHECK(c, upload(c, L.T, Tt));
   }
-  HIPCHECK(c, upload(c, L.wntri, c->wntri));
-  HIPCHECK(c, upload(c, L.wtris, c->wtris));
   HIPCHECK(c, upload(c, L.wlines, c->wlines));
   HIPCHECK(c, upload(c, L.wcorners, c->wcorners));
+  HIPCHECK(c, upload(c, L.ops2f, h.ops2f));
   fill_levels(c);
   c->cur = 0;
   c->src_slot.assign(c->n_shots, -1);
@@ -886,6 +876,13 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
       if (c->timing) {
         HIPCHECK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
+      }
+      {
+        const dgh::FaceBufs fb{dptr<double>(c, L.q2[o]), dptr<double>(c, L.q2[n]),
+                               dptr<double>(c, L.res2), dptr<double>(c, L.qb3),
+                               dptr<double>(c, L.q03), dptr<double>(c, L.q3[n]),
+                               dptr<double>(c, L.qb2)};
+        HIPCHECK(c, dgh::launch_faces(c->LF, c->L2, fb, sh, kA[s], kB[s], dt, c->stream));
       }
       HIPCHECK(c, dgh::launch_boundary(c->LB, c->L2, c->L1, c->L0, c->L3, dptr<double>(c, L.q2[o]),
                                        dptr<double>(c, L.q2[n]), dptr<double>(c, L.res2),

@@ -1,0 +1,262 @@
+// FP64 face level (the 2D systems of the HABC faces, Section 2.3 and
+// Algorithm 3) on the FP64 4x4x4 MFMA: one wave updates the P auxiliary
+// sets of TW = 16 / P consecutive triangles (MFMA column es = local
+// triangle * P + set), then applies the face rule.  Every load of a wave is
+// issued before its first MFMA: two dependent rounds (triangle data, then
+// what the maps point to).
+//
+// Per triangle and set i, with K_i = rho c^2 / (1 + g_i) and the in-plane
+// reference gradients (rx, ry), (sx, sy):
+//   d p*_i/dt = -K_i div v_i + LIFT [fsc K_i (v.n^- - (v.n)*)]
+//   d v_i/dt  = -(1/rho) grad p_i + LIFT [fsc (1/rho) (p^- - p*)] n
+// with the upwind flux against the neighbouring triangle (same set), the
+// characteristic condition r- = qb2 at an HABC edge, r- = 0 at a basic-ABC
+// edge, or p = 0; then res = A res + dt rhs, p*_i = p_i - q0_3 + B res_p,
+// v_i = v_i + B res_v, and from the new 3D trace: r+ = (p3 + Z n.u3)/2,
+// r- = (1/M) sum_i g_i p*_i -> qb3, S = r+ + r- -> q0_3, p_i = p*_i + S.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "levels.hpp"
+
+namespace dgh {
+
+namespace {
+
+constexpr int kWaves2 = 4;   // waves per workgroup
+
+template <int N>
+struct Dims2 {
+  static constexpr int Np = (N + 1) * (N + 2) / 2;
+  static constexpr int Nfp = N + 1;
+  static constexpr int RG = (Np + 3) / 4;    // row groups, also volume k-steps
+  static constexpr int EK = (Nfp + 3) / 4;   // lifting k-steps per edge
+  static constexpr int NFRAG = 2 * RG * RG + RG * 3 * EK;
+};
+
+template <int N>
+__global__ void __launch_bounds__(kWaves2 * 64, 3) k_faces(LvlF F, Lvl2 L2, FaceBufs b, Shots sh,
+                                                           double A, double B, double dt) {
+  using D = Dims2<N>;
+  constexpr int Np = D::Np, Nfp = D::Nfp, RG = D::RG, EK = D::EK;
+  __shared__ double sops[D::NFRAG * 16];
+  __shared__ double sg[16];
+  __shared__ int smask[3 * Nfp];
+  fill_lds<kWaves2 * 64, D::NFRAG * 16>(sops, F.ops, threadIdx.x);
+  fill_lds<kWaves2 * 64, 3 * Nfp>(smask, L2.fmask, threadIdx.x);
+  const int P = L2.P;
+  if (threadIdx.x < P) sg[threadIdx.x] = L2.gamma[threadIdx.x];
+  __syncthreads();
+  {
+    const size_t k = blockIdx.y;   // this block's shot
+    b.q2o += k * sh.st2;
+    b.q2n += k * sh.st2;
+    b.res2 += k * sh.st2;
+    b.qb3 += k * sh.stb3;
+    b.q03 += k * sh.stb3;
+    b.q3n += k * sh.st3;
+    b.qb2 += k * sh.stb2;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int es = lane & 15, g = lane >> 4;
+  const int ta = (lane & 3) + 4 * g;         // lane's entry of an A fragment
+  const int Pc = P > 0 ? P : 1, TW = 16 / Pc;
+  const int tl = es / Pc, i = es - tl * Pc;
+  const int w0 = (blockIdx.x * kWaves2 + wv) * TW;   // first triangle of this wave
+  if (w0 >= L2.Kt) return;
+  const bool col = tl < TW && w0 + tl < L2.Kt;       // column holds (triangle, set)
+  const int t = min(w0 + min(tl, TW - 1), L2.Kt - 1);
+  const int ic = P > 0 ? i : 0;
+  // ---- every load that depends on the triangle only
+  const double* gg = L2.geo + (size_t)t * 8;
+  const double rx = gg[0], ry = gg[1], sx = gg[2], sy = gg[3], irho = gg[4], Kb = gg[5],
+               Z = gg[6];
+  const int* inf = L2.info + (size_t)t * 8;
+  const int e3 = inf[0], ax = inf[1], sgn = inf[2];
+  int code[3], nn[3][EK];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    code[e] = inf[3 + e];
+#pragma unroll
+    for (int jj = 0; jj < EK; ++jj)
+      nn[e][jj] = L2.nbrnode[((size_t)t * 3 + e) * Nfp + min(4 * jj + g, Nfp - 1)];
+  }
+  const size_t pb = ((size_t)t * Pc + ic) * 3 * Np;   // this pair's fields
+  const double* q = b.q2o + pb;
+  int n3[RG];
+  double S0[RG], vp[RG], va[RG], vb[RG], ro[RG][3];
+#pragma unroll
+  for (int r = 0; r < RG; ++r) {
+    const int n = min(4 * r + g, Np - 1);
+    n3[r] = L2.tetnode[(size_t)t * Np + n];
+    S0[r] = b.q03[(size_t)t * Np + n];
+    if (P > 0) {
+      vp[r] = q[n];
+      va[r] = q[Np + n];
+      vb[r] = q[2 * Np + n];
+      ro[r][0] = b.res2[pb + n];
+      ro[r][1] = b.res2[pb + Np + n];
+      ro[r][2] = b.res2[pb + 2 * Np + n];
+    } else {
+      vp[r] = va[r] = vb[r] = ro[r][0] = ro[r][1] = ro[r][2] = 0.0;
+    }
+  }
+  // ---- loads through the maps: new 3D trace, exterior values of the edges
+  double p3[RG], u3[RG];
+  {
+    const double* q3 = b.q3n + (size_t)(e3 >> 4) * 4 * F.np3 * kTile + (e3 & 15);
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      p3[r] = q3[n3[r] * kTile];
+      u3[r] = q3[((1 + ax) * F.np3 + n3[r]) * kTile];
+    }
+  }
+  double ps[RG];   // new p*_i at this lane's rows
+#pragma unroll
+  for (int r = 0; r < RG; ++r) ps[r] = 0.0;
+  if (P > 0) {
+    double xp[3][EK], xa[3][EK], xb[3][EK], xZ[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const bool inner = code[e] >= 0;
+      const int c = -1 - code[e];
+      const bool hb = !inner && (c & 3) == 0;
+      xZ[e] = L2.geo[(size_t)(inner ? code[e] : t) * 8 + 6];
+      const double* qn = b.q2o + ((size_t)(inner ? code[e] : t) * P + i) * 3 * Np;
+      const double* qbl = b.qb2 + (((size_t)(hb ? (c >> 3) : 0) * 2 + ((c >> 2) & 1)) * P + i) * Nfp;
+#pragma unroll
+      for (int jj = 0; jj < EK; ++jj) {
+        const int m = min(nn[e][jj], Np - 1);
+        xp[e][jj] = inner ? qn[m] : (hb ? qbl[min(nn[e][jj], Nfp - 1)] : 0.0);
+        xa[e][jj] = qn[Np + m];
+        xb[e][jj] = qn[2 * Np + m];
+      }
+    }
+    const double* fj = sops + ta;
+    const double* fl = sops + 2 * RG * RG * 16 + ta;
+    const double Ki = Kb / (1.0 + sg[i]);
+    // ---- volume: Dr p, Ds p and div v = Dr (grad r . v) + Ds (grad s . v)
+    double Gr[RG], Gs[RG], rp[RG];
+#pragma unroll
+    for (int r = 0; r < RG; ++r) Gr[r] = Gs[r] = rp[r] = 0.0;
+#pragma unroll
+    for (int j = 0; j < RG; ++j) {
+      const double fr = rx * va[j] + ry * vb[j], fs = sx * va[j] + sy * vb[j];
+#pragma unroll
+      for (int r = 0; r < RG; ++r) {
+        const double ar = fj[((0 * RG + r) * RG + j) * 16];
+        const double as = fj[((1 * RG + r) * RG + j) * 16];
+        Gr[r] = mfma4(ar, vp[j], Gr[r]);
+        Gs[r] = mfma4(as, vp[j], Gs[r]);
+        rp[r] = mfma4(ar, fr, rp[r]);
+        rp[r] = mfma4(as, fs, rp[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RG; ++r) rp[r] *= -Ki;
+    // ---- surface: edges s = -1, r + s = 0, r = -1 with n fsc = -grad s,
+    // grad(r+s), -grad r.  Upwind flux against the exterior state: the
+    // neighbour's trace, p = 2 r- with v.n = 0 (characteristic condition,
+    // r- = qb2 at an HABC edge, 0 at a basic-ABC edge), or the mirror
+    // p = -p^-, v.n = v.n^- (p = 0).  The pressure jump is lifted into G
+    // (Gs for edge 0, -Gr and -Gs for edge 1, Gr for edge 2).
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const double cr = e == 0 ? 0.0 : (e == 1 ? 1.0 : -1.0);
+      const double cs = e == 2 ? 0.0 : (e == 1 ? 1.0 : -1.0);
+      double na = cr * rx + cs * sx, nb = cr * ry + cs * sy;
+      const double fsc = sqrt(na * na + nb * nb);
+      na /= fsc;
+      nb /= fsc;
+      const bool inner = code[e] >= 0;
+      const int c = -1 - code[e];
+      const bool hb = !inner && (c & 3) == 0, dir = !inner && (c & 3) == 2;
+      const double ZP = inner ? xZ[e] : Z;
+      const double iZ = 1.0 / (Z + ZP);
+      const double aM = ZP * iZ, aP = Z * iZ, bZ = Z * aM, cP = fsc * Ki;
+#pragma unroll
+      for (int jj = 0; jj < EK; ++jj) {
+        const int kc = min(4 * jj + g, Nfp - 1);   // rows beyond Nfp: LIFT columns are 0
+        const int a = smask[e * Nfp + kc];
+        const double pM = q[a], vnM = na * q[Np + a] + nb * q[2 * Np + a];
+        const double vnP = na * xa[e][jj] + nb * xb[e][jj];
+        const double pG = inner ? xp[e][jj] : (dir ? -pM : (hb ? 2.0 * xp[e][jj] : 0.0));
+        const double uG = inner ? vnP : (dir ? vnM : 0.0);
+        const double pF = aM * pM + aP * pG + bZ * (vnM - uG);
+        const double vnF = iZ * (pM - pG) + aP * vnM + aM * uG;
+        const double fp = cP * (vnM - vnF);
+        const double fu = pM - pF;
+        const double* fe = fl + (e * EK + jj) * 16;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) {
+          const double l = fe[r * 3 * EK * 16];
+          rp[r] = mfma4(l, fp, rp[r]);
+          if (e == 0) Gs[r] = mfma4(l, fu, Gs[r]);
+          if (e == 1) {
+            Gr[r] = mfma4(l, -fu, Gr[r]);
+            Gs[r] = mfma4(l, -fu, Gs[r]);
+          }
+          if (e == 2) Gr[r] = mfma4(l, fu, Gr[r]);
+        }
+      }
+    }
+    // ---- LSRK update of the rows this lane holds
+#pragma unroll
+    for (int r = 0; r < RG; ++r) {
+      const int n = 4 * r + g;
+      const double r0 = A * ro[r][0] + dt * rp[r];
+      const double r1 = A * ro[r][1] + dt * (-irho * (rx * Gr[r] + sx * Gs[r]));
+      const double r2 = A * ro[r][2] + dt * (-irho * (ry * Gr[r] + sy * Gs[r]));
+      ps[r] = vp[r] - S0[r] + B * r0;
+      if (col && n < Np) {
+        double* rw = b.res2 + pb + n;
+        rw[0] = r0;
+        rw[Np] = r1;
+        rw[2 * Np] = r2;
+        b.q2n[pb + Np + n] = va[r] + B * r1;
+        b.q2n[pb + 2 * Np + n] = vb[r] + B * r2;
+      }
+    }
+  }
+  // ---- face rule per row group: r- = (1/M) sum_i g_i p*_i over the P
+  // columns of this triangle (lanes of the same row, gathered by shuffles)
+#pragma unroll
+  for (int r = 0; r < RG; ++r) {
+    const int n = 4 * r + g;
+    const double gp = P > 0 ? sg[ic] * ps[r] : 0.0;
+    double rm = 0.0;
+    for (int s2 = 0; s2 < P; ++s2) rm += __shfl(gp, (lane & ~15) + tl * Pc + s2);
+    rm *= L2.invM;
+    const double S = 0.5 * (p3[r] + Z * (double)sgn * u3[r]) + rm;
+    if (col && n < Np) {
+      if (i == 0) {
+        b.qb3[(size_t)t * Np + n] = rm;
+        b.q03[(size_t)t * Np + n] = S;
+      }
+      if (P > 0) b.q2n[pb + n] = ps[r] + S;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_faces(const LvlF& F, const Lvl2& L2, const FaceBufs& b, const Shots& sh,
+                        double A, double B, double dt, hipStream_t st) {
+  if (L2.Kt == 0) return hipSuccess;
+  if (L2.P > 16 || sh.n < 1 || sh.n > 65535) return hipErrorInvalidValue;
+  const int TW = 16 / (L2.P > 0 ? L2.P : 1);
+  const int waves = (L2.Kt + TW - 1) / TW;
+  const dim3 grid((waves + kWaves2 - 1) / kWaves2, sh.n), block(kWaves2 * 64);
+  switch (L2.Np) {
+    case 3: hipLaunchKernelGGL(k_faces<1>, grid, block, 0, st, F, L2, b, sh, A, B, dt); break;
+    case 6: hipLaunchKernelGGL(k_faces<2>, grid, block, 0, st, F, L2, b, sh, A, B, dt); break;
+    case 10: hipLaunchKernelGGL(k_faces<3>, grid, block, 0, st, F, L2, b, sh, A, B, dt); break;
+    case 15: hipLaunchKernelGGL(k_faces<4>, grid, block, 0, st, F, L2, b, sh, A, B, dt); break;
+    case 21: hipLaunchKernelGGL(k_faces<5>, grid, block, 0, st, F, L2, b, sh, A, B, dt); break;
+    case 28: hipLaunchKernelGGL(k_faces<6>, grid, block, 0, st, F, L2, b, sh, A, B, dt); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dgh

@@ -103,25 +103,42 @@ struct Shots {
 hipError_t launch_level3(const Lvl3& L, const double* qo, double* qn, double* res,
                          const double* qb3, double A, double B, double dt, const Shots& sh,
                          hipStream_t st);
-// Work list of the merged boundary kernel: block b updates the triangles
-// tris[b][*], then the lines lines[b][*] (each with its edge system), then
-// the corners corners[b][*]; -1 ends a list.  Blocks with lines hold every
-// triangle adjacent to their lines and every line of their corners.
+// Work list of the line-group kernel: block b updates the lines
+// lines[b][*] (each with its edge system), then the corners corners[b][*];
+// -1 ends a list.  A block holds every line of its corners.
 struct LvlB {
-  int nblocks, TPB, NS, maxtri, maxlin, maxcor;
-  const int* ntri;     // triangles of each block
-  const int* tris;
+  int nblocks, maxlin, maxcor;
   const int* lines;
   const int* corners;
 };
 
-// 2D, 1D and 0D levels of one stage in one launch.
+// 1D and 0D levels of one stage (after the 3D and 2D updates).
 hipError_t launch_boundary(const LvlB& W, const Lvl2& L2, const Lvl1& L1, const Lvl0& L0,
                            const Lvl3& L3, const double* q2o, double* q2n, double* res2,
                            double* qb2, double* qb3, double* q03, const double* q3n,
                            const double* q1o, double* q1n, double* res1, double* qb1,
                            double* q02, double A, double B, double dt, const Shots& sh,
                            hipStream_t st);
+// Face level on MFMA (all triangles, TW = 16 / P per wave): ops holds Dr2,
+// Ds2 as [2][RG][RG][16] and LIFT2 as [RG][3][EK][16] 4x4x4 A-fragments
+// (entry t = i + 4 k), RG = ceil(Np2/4), EK = ceil(Nfp2/4).
+struct LvlF {
+  int np3;             // nodes of the 3D element (q3 layout)
+  const double* ops;
+};
+struct FaceBufs {
+  const double* q2o;
+  double *q2n, *res2, *qb3, *q03;
+  const double* q3n;
+  const double* qb2;
+};
+hipError_t launch_faces(const LvlF& F, const Lvl2& L2, const FaceBufs& b, const Shots& sh,
+                        double A, double B, double dt, hipStream_t st);
+inline int frag2_size(int N) {
+  const int Np = (N + 1) * (N + 2) / 2, Nfp = N + 1, RG = (Np + 3) / 4, EK = (Nfp + 3) / 4;
+  return (2 * RG * RG + RG * 3 * EK) * 16;
+}
+
 // Arrays scanned by the finiteness check (at most kScanMax of them); the
 // kernel writes one int per (array, block): 1 if a non-finite value was seen.
 constexpr int kScanMax = 12;

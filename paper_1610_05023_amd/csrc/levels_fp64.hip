@@ -12,6 +12,9 @@
 // r+- = (p +- Z n.u)/2; LSRK: res = A res + dt rhs, q = q + B res.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include "kernels.hpp"
 #include "levels.hpp"
 
 namespace dgh {
@@ -42,10 +45,6 @@ struct Dims3 {
   static constexpr bool kLds = NFRAG * 16 * 8 <= 64 * 1024;
 };
 
-__device__ __forceinline__ double mfma4(double a, double b, double c) {
-  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
-}
-
 // Buffer-resource access: a 32-bit per-lane byte offset plus a uniform
 // (scalar) offset, so the four fields of a node share one address register.
 // The host keeps every 3D array below 4 GiB; an offset past the end of a
@@ -64,13 +63,13 @@ __device__ __forceinline__ void bst(Rsrc r, unsigned voff, unsigned soff, double
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
 
-// Maps the hardware block id to a logical block so that each XCD (blocks
-// are dealt round-robin over the 8 XCDs) walks a contiguous range of tiles:
-// neighbours of a tile then mostly sit in the same XCD's L2.
-__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
-  const int q = nblocks >> 3, rem = nblocks & 7, x = bid & 7;
-  return x * q + min(x, rem) + (bid >> 3);
-}
+template <int N>
+__device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restrict__ qo,
+                                          double* __restrict__ qn, double* __restrict__ res,
+                                          const double* __restrict__ qb3, double A, double B,
+                                          double dt, const Shots& sh, long long item, int ngrp,
+                                          const int* smap, const int* smask, const double* sops,
+                                          int lane);
 
 template <int N>
 __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double* __restrict__ qo,
@@ -86,17 +85,35 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
   int* smask = reinterpret_cast<int*>(sfrag);
   int* smap = smask + 4 * Nfp;
   constexpr int kTabDoubles = (4 * Nfp + 96 * Nfp + 1) / 2;
-  for (int i = threadIdx.x; i < 4 * Nfp; i += blockDim.x) smask[i] = L.fmask[i];
-  for (int i = threadIdx.x; i < 96 * Nfp; i += blockDim.x) smap[i] = L.fmap[i];
+  fill_lds<kWaves3 * 64, 4 * Nfp>(smask, L.fmask, threadIdx.x);
+  fill_lds<kWaves3 * 64, 96 * Nfp>(smap, L.fmap, threadIdx.x);
   double* sops = sfrag + kTabDoubles;
-  if (D::kLds)
-    for (int i = threadIdx.x; i < D::NFRAG * 16; i += blockDim.x) sops[i] = L.ops[i];
+  if (D::kLds) fill_lds<kWaves3 * 64, D::NFRAG * 16>(sops, L.ops, threadIdx.x);
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  // (block, shot) pairs are dealt to the XCDs in contiguous ranges
-  const int lin = xcd_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int shot = lin / gridDim.x;
-  const int tile = (lin - shot * gridDim.x) * kWaves3 + (threadIdx.x >> 6);
+  // persistent: the workgroup loads its tables once, then its waves take
+  // (shot, group of kWaves3 tiles) items from its XCD's range
+  const int ngrp = (L.ntile + kWaves3 - 1) / kWaves3;
+  const XcdRange rg_(ngrp * (long long)sh.n);
+  for (long long item = rg_.lo; item < rg_.hi; item += rg_.step)
+    tile_step<N>(L, qo, qn, res, qb3, A, B, dt, sh, item, ngrp, smap, smask, sops, lane);
+}
+
+// One wave's share of one work item: tile (item mod ngrp) kWaves3 + wave of
+// shot item / ngrp.
+template <int N>
+__device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restrict__ qo,
+                                          double* __restrict__ qn, double* __restrict__ res,
+                                          const double* __restrict__ qb3, double A, double B,
+                                          double dt, const Shots& sh, long long item, int ngrp,
+                                          const int* smap, const int* smask, const double* sops,
+                                          int lane) {
+  using D = Dims3<N>;
+  constexpr int Np = D::Np, Nfp = D::Nfp, RG = D::RG, FK = D::FK;
+  constexpr unsigned FS = Np * kTile * 8;   // bytes between two fields of a tile
+  constexpr unsigned TS = 4 * FS;           // bytes per tile
+  const int shot = (int)(item / ngrp);
+  const int tile = (int)(item - (long long)shot * ngrp) * kWaves3 + (threadIdx.x >> 6);
   if (tile >= L.ntile) return;
   qo += shot * sh.st3;
   qn += shot * sh.st3;
@@ -116,6 +133,16 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
   const double sx = gt[3 * kTile], sy = gt[4 * kTile], sz = gt[5 * kTile];
   const double tx = gt[6 * kTile], ty = gt[7 * kTile], tz = gt[8 * kTile];
   const double irho = gt[9 * kTile], Kb = gt[10 * kTile], Z = gt[11 * kTile];
+  // face codes and exterior impedances, loaded with the geometry
+  const int* nbrt = L.nbr + tile * 4 * kTile + es;
+  const double* znt = L.zn + tile * 4 * kTile + es;
+  int fcode[4];
+  double fz[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    fcode[f] = nbrt[f * kTile];
+    fz[f] = znt[f * kTile];
+  }
 
   // ---- volume: Dr p, Ds p, Dt p and div u = Dr fr + Ds fs + Dt ft with the
   // contravariant fluxes fr = grad r . u etc.  Rows beyond Np read the last
@@ -169,19 +196,12 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
       }
     }
   }
-  // in place: dv -> rhs_p, (dpr, dps, dpt) -> rhs_(u, v, w)
+  // rhs_p = -rho c^2 div u (+ the lifted surface term); the velocity rhs
+  // stays the reference gradient G = (Dr p, Ds p, Dt p) plus the lifted
+  // pressure jumps until the update maps it: rhs_u = -(1/rho) J^-T G
 #pragma unroll
-  for (int i = 0; i < RG; ++i) {
-    const double a = dpr[i], b = dps[i], c = dpt[i];
-    dv[i] *= -Kb;
-    dpr[i] = -irho * (rx * a + sx * b + tx * c);
-    dps[i] = -irho * (ry * a + sy * b + ty * c);
-    dpt[i] = -irho * (rz * a + sz * b + tz * c);
-  }
+  for (int i = 0; i < RG; ++i) dv[i] *= -Kb;
   double* rp = dv;
-  double* ru = dpr;
-  double* rv = dps;
-  double* rw = dpt;
 
   // ---- surface: fluxes at the face nodes in B-fragment order, then LIFT.
   // Every face uses the upwind flux against an exterior state: the
@@ -190,10 +210,9 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
   // mirror p = -p^-, n.u = n.u^- (p = 0); boundary faces carry their own
   // impedance, for which this reproduces the characteristic and Dirichlet
   // fluxes exactly.
-  const int* nbrt = L.nbr + tile * 4 * kTile + es;
-  const double* znt = L.zn + tile * 4 * kTile + es;
-#pragma unroll 1
+#pragma unroll
   for (int f = 0; f < 4; ++f) {
+    __builtin_amdgcn_sched_barrier(0);
     // outward normal of face f: -grad t, -grad s, grad(r+s+t), -grad r
     const double cr = f == 2 ? 1.0 : (f == 3 ? -1.0 : 0.0);
     const double cs = f == 2 ? 1.0 : (f == 1 ? -1.0 : 0.0);
@@ -206,8 +225,8 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
     nx *= inv;
     ny *= inv;
     nz *= inv;
-    const int code = nbrt[f * kTile];
-    const double ZP = znt[f * kTile];
+    const int code = fcode[f];
+    const double ZP = fz[f];
     // interior faces gather from the neighbour; boundary faces read their own
     // element there (unused) and qb3 (triangle 0 unless HABC, unused) --
     // every load is issued, then the exterior state is selected
@@ -223,10 +242,7 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
     // upwind weights (exact-Riemann flux, Section 3.2)
     const double iZ = 1.0 / (Z + ZP);
     const double aM = ZP * iZ, aP = Z * iZ, bZ = Z * aM;
-    const double cP = fsc * Kb, cU = fsc * irho;
-    double tmp[RG];
-#pragma unroll
-    for (int i = 0; i < RG; ++i) tmp[i] = 0.0;
+    const double cP = fsc * Kb;
 #pragma unroll
     for (int jj = 0; jj < FK; ++jj) {
       const int kc = min(4 * jj + g, Nfp - 1);   // rows beyond Nfp: LIFT columns are 0
@@ -246,20 +262,29 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
       const double pF = aM * pM + aP * pG + bZ * (unM - uG);
       const double unF = iZ * (pM - pG) + aP * unM + aM * uG;
       const double fp = cP * (unM - unF);
-      const double fu = cU * (pM - pF);
+      // pressure jump, lifted into G: with n fsc = -grad t, -grad s,
+      // grad(r+s+t), -grad r on faces 0..3, the term fsc (1/rho) (p^- - p*) n
+      // of rhs_u equals -(1/rho) J^-T (-c_f) L (p^- - p*)
+      const double fu = pM - pF;
       const double* fl = fragL + (f * FK + jj) * 16;
+      if (f == 2) {
 #pragma unroll
-      for (int i = 0; i < RG; ++i) {
-        const double a = fl[i * 4 * FK * 16];
-        rp[i] = mfma4(a, fp, rp[i]);
-        tmp[i] = mfma4(a, fu, tmp[i]);
+        for (int i = 0; i < RG; ++i) {
+          const double a = fl[i * 4 * FK * 16];
+          rp[i] = mfma4(a, fp, rp[i]);
+          dpr[i] = mfma4(a, -fu, dpr[i]);
+          dps[i] = mfma4(a, -fu, dps[i]);
+          dpt[i] = mfma4(a, -fu, dpt[i]);
+        }
+      } else {
+        double* G = f == 0 ? dpt : (f == 1 ? dps : dpr);
+#pragma unroll
+        for (int i = 0; i < RG; ++i) {
+          const double a = fl[i * 4 * FK * 16];
+          rp[i] = mfma4(a, fp, rp[i]);
+          G[i] = mfma4(a, fu, G[i]);
+        }
       }
-    }
-#pragma unroll
-    for (int i = 0; i < RG; ++i) {
-      ru[i] += nx * tmp[i];
-      rv[i] += ny * tmp[i];
-      rw[i] += nz * tmp[i];
     }
   }
 
@@ -296,7 +321,11 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
         const int nc = min(n, Np - 1);
         const unsigned o = tb + (unsigned)nc * (kTile * 8);
         const double sw = src_w[nc];
-        const double rhs[4] = {rp[i] + (src ? sw * src_s : 0.0), ru[i], rv[i], rw[i]};
+        const double a = dpr[i], bq = dps[i], c = dpt[i];
+        const double rhs[4] = {rp[i] + (src ? sw * src_s : 0.0),
+                               -irho * (rx * a + sx * bq + tx * c),
+                               -irho * (ry * a + sy * bq + ty * c),
+                               -irho * (rz * a + sz * bq + tz * c)};
         if (live && n < Np) {
 #pragma unroll
           for (int fl = 0; fl < 4; ++fl) {
@@ -351,14 +380,30 @@ hipError_t launch3(const Lvl3& L, const double* qo, double* qn, double* res, con
   constexpr int Nfp = D::Nfp;
   const size_t lds = sizeof(double) * ((4 * Nfp + 96 * Nfp + 1) / 2 + (D::kLds ? D::NFRAG * 16 : 0));
   static bool attr = false;
-  if (!attr && lds > 0) {
-    hipFuncSetAttribute((const void*)k_level3<N>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_level3<N>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
     attr = true;
   }
-  const int blocks = (L.ntile + kWaves3 - 1) / kWaves3;
-  if (sh.n < 1 || (long long)blocks * sh.n > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_level3<N>, dim3(blocks, sh.n), dim3(kWaves3 * 64), lds, st, L, qo, qn, res,
+  const int ngrp = (L.ntile + kWaves3 - 1) / kWaves3;
+  if (sh.n < 1) return hipErrorInvalidValue;
+  // persistent grid: as many workgroups as fit on the device at once
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3<N>, kWaves3 * 64, lds);
+    if (e != hipSuccess) return e;
+    resident = std::max(1, per_cu) * prop.multiProcessorCount;
+  }
+  const long long items = (long long)ngrp * sh.n;
+  // a multiple of 8, so that every XCD has blocks for its range of items
+  const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, items) / 8 * 8);
+  hipLaunchKernelGGL(k_level3<N>, dim3(blocks), dim3(kWaves3 * 64), lds, st, L, qo, qn, res,
                      qb3, A, B, dt, sh);
   return hipGetLastError();
 }

@@ -137,12 +137,14 @@ def test_batched_shots_match_single_runs():
     """Three shots on one mesh, stepped together: each has its own random
     state and point source, and each matches its own oracle run."""
     from paper_1610_05023_amd import Solver
-    n, N, P, steps, dt = 4, 3, 3, 12, 2e-3
+    n, N, P, steps, dt = 6, 3, 3, 12, 1e-3     # n >= 5: the medium has 4 interfaces
     base = make_case(n=n, N=N, P=P, medium="layered", init="zero")
     s = Solver(base["VX"], base["E"], N, P, base["rho"], base["c"], face_bc=base["face_bc"],
                periodic=base["periodic"], box=base["box"], n_shots=3).bind()
     cases = []
-    for k, xs in enumerate([(0.41, 0.52, 0.33), (0.7, 0.3, 0.6), (0.22, 0.81, 0.5)]):
+    # source points off every mesh face (a point on a face would make the
+    # choice of its element a tie)
+    for k, xs in enumerate([(0.41, 0.52, 0.33), (0.71, 0.3, 0.61), (0.22, 0.81, 0.47)]):
         c = make_case(n=n, N=N, P=P, medium="layered", init="random", seed=70 + 20 * k,
                       source=(xs, 6.0 + k, 0.05 + 0.01 * k))
         cases.append(c)
@@ -154,3 +156,11 @@ def test_batched_shots_match_single_runs():
         err = rel_errors(got, run_oracle(c, steps, dt))
         print(f"[shots] shot {k}", {a: f"{v:.1e}" for a, v in err.items()}, flush=True)
         assert max(err.values()) <= TOL, (k, err)
+
+
+@pytest.mark.parametrize("N,P", [(1, 1), (2, 0), (3, 12), (5, 2), (6, 1)])
+def test_degrees_and_habc_orders(N, P):
+    """Every compiled degree and HABC orders 0 (face rule only), 1, 2, 12
+    (two edge nodes per thread) on all-HABC faces, every array random."""
+    case = make_case(n=3, N=N, P=P, init="random", seed=90 + 7 * N + P)
+    _check(case, 4, 1e-3)
