@@ -387,10 +387,12 @@ void compute_layout(dgh_ctx* c) {
   // every state array holds n_shots shots, each starting 256-byte aligned
   const int Kt = m.Ktri, Np2 = m.tri.Np, Nfp2 = m.tri.Nfp, Kl = m.Klin, Np1 = m.line.Np;
   L.st3 = round32((size_t)nt * 4 * Np * T);
-  L.st2 = round32((size_t)Kt * P * 3 * Np2);
+  // at least one set of one triangle (read, unused, by the face kernel at P = 0)
+  L.st2 = round32((size_t)Kt * std::max(P, 1) * 3 * Np2);
   L.stb3 = round32(std::max<size_t>(Nfp, (size_t)Kt * Np2));  // >= one triangle (read masked)
   L.st1 = round32((size_t)Kl * P * P * 2 * Np1);
-  L.stb2 = round32((size_t)Kl * 2 * P * Np1);
+  // at least one line, so that the face kernel may read line 0 of qb2
+  L.stb2 = round32((size_t)std::max(Kl, 1) * 2 * std::max(P, 1) * Np1);
   L.stb1 = round32((size_t)m.Kpnt * 3 * P * P);
   L.add(L.q3[0], S * L.st3 * d);
   L.add(L.q3[1], S * L.st3 * d);

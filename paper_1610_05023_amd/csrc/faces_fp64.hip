@@ -35,13 +35,16 @@ struct Dims2 {
 };
 
 template <int N>
-__global__ void __launch_bounds__(kWaves2 * 64, 3) k_faces(LvlF F, Lvl2 L2, FaceBufs b, Shots sh,
+__global__ void __launch_bounds__(kWaves2 * 64, 2) k_faces(LvlF F, Lvl2 L2, FaceBufs b, Shots sh,
                                                            double A, double B, double dt) {
   using D = Dims2<N>;
   constexpr int Np = D::Np, Nfp = D::Nfp, RG = D::RG, EK = D::EK;
+  constexpr int SPAN = 16 * 3 * Np;          // fields of at most 16 (triangle, set) pairs
+  constexpr int KL = (SPAN + 63) / 64;       // linear loads per lane
   __shared__ double sops[D::NFRAG * 16];
   __shared__ double sg[16];
   __shared__ int smask[3 * Nfp];
+  __shared__ double sbuf[kWaves2][2][SPAN];  // per wave: q2 and res2 of its pairs
   fill_lds<kWaves2 * 64, D::NFRAG * 16>(sops, F.ops, threadIdx.x);
   fill_lds<kWaves2 * 64, 3 * Nfp>(smask, L2.fmask, threadIdx.x);
   const int P = L2.P;
@@ -64,10 +67,25 @@ __global__ void __launch_bounds__(kWaves2 * 64, 3) k_faces(LvlF F, Lvl2 L2, Face
   const int tl = es / Pc, i = es - tl * Pc;
   const int w0 = (blockIdx.x * kWaves2 + wv) * TW;   // first triangle of this wave
   if (w0 >= L2.Kt) return;
-  const bool col = tl < TW && w0 + tl < L2.Kt;       // column holds (triangle, set)
-  const int t = min(w0 + min(tl, TW - 1), L2.Kt - 1);
+  const int ntw = min(TW, L2.Kt - w0);               // triangles of this wave
+  const bool col = tl < ntw;                         // column holds (triangle, set)
+  const int t = w0 + min(tl, ntw - 1);
   const int ic = P > 0 ? i : 0;
-  // ---- every load that depends on the triangle only
+  // ---- the wave's pairs are contiguous in q2 and res2: staged through LDS
+  // with linear (coalesced) loads and, at the end, stores
+  double* sq = sbuf[wv][0];
+  double* sr = sbuf[wv][1];
+  const int cnt = ntw * P * 3 * Np;
+  const size_t wbase = (size_t)w0 * P * 3 * Np;
+  if (P > 0) {
+    double vq[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) vq[k] = b.q2o[wbase + min(lane + 64 * k, cnt - 1)];
+#pragma unroll
+    for (int k = 0; k < KL; ++k)
+      if (lane + 64 * k < cnt) sq[lane + 64 * k] = vq[k];
+  }
+  // ---- every other load that depends on the triangle only
   const double* gg = L2.geo + (size_t)t * 8;
   const double rx = gg[0], ry = gg[1], sx = gg[2], sy = gg[3], irho = gg[4], Kb = gg[5],
                Z = gg[6];
@@ -81,25 +99,13 @@ __global__ void __launch_bounds__(kWaves2 * 64, 3) k_faces(LvlF F, Lvl2 L2, Face
     for (int jj = 0; jj < EK; ++jj)
       nn[e][jj] = L2.nbrnode[((size_t)t * 3 + e) * Nfp + min(4 * jj + g, Nfp - 1)];
   }
-  const size_t pb = ((size_t)t * Pc + ic) * 3 * Np;   // this pair's fields
-  const double* q = b.q2o + pb;
   int n3[RG];
-  double S0[RG], vp[RG], va[RG], vb[RG], ro[RG][3];
+  double S0[RG];
 #pragma unroll
   for (int r = 0; r < RG; ++r) {
     const int n = min(4 * r + g, Np - 1);
     n3[r] = L2.tetnode[(size_t)t * Np + n];
     S0[r] = b.q03[(size_t)t * Np + n];
-    if (P > 0) {
-      vp[r] = q[n];
-      va[r] = q[Np + n];
-      vb[r] = q[2 * Np + n];
-      ro[r][0] = b.res2[pb + n];
-      ro[r][1] = b.res2[pb + Np + n];
-      ro[r][2] = b.res2[pb + 2 * Np + n];
-    } else {
-      vp[r] = va[r] = vb[r] = ro[r][0] = ro[r][1] = ro[r][2] = 0.0;
-    }
   }
   // ---- loads through the maps: new 3D trace, exterior values of the edges
   double p3[RG], u3[RG];
@@ -111,30 +117,49 @@ __global__ void __launch_bounds__(kWaves2 * 64, 3) k_faces(LvlF F, Lvl2 L2, Face
       u3[r] = q3[((1 + ax) * F.np3 + n3[r]) * kTile];
     }
   }
+  // every load is issued at an address valid for any edge kind (own
+  // triangle, line 0 of qb2) and the values are selected afterwards, so
+  // that no load waits behind a branch on loaded data
+  double xp[3][EK], xa[3][EK], xb[3][EK], xZ[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const bool inner = code[e] >= 0;
+    const int c = -1 - code[e];
+    const bool hb = !inner && (c & 3) == 0;
+    const int tn = inner ? code[e] : t;
+    const int lq = hb ? (c >> 3) : 0, sd = hb ? ((c >> 2) & 1) : 0;
+    xZ[e] = L2.geo[(size_t)tn * 8 + 6];
+    const double* qn = b.q2o + (P > 0 ? ((size_t)tn * P + i) * 3 * Np : 0);
+    const double* qbl = b.qb2 + (((size_t)lq * 2 + sd) * Pc + ic) * Nfp;
+#pragma unroll
+    for (int jj = 0; jj < EK; ++jj) {
+      const int m = min(nn[e][jj], Np - 1);
+      const double a0 = qn[m], rb = qbl[min(nn[e][jj], Nfp - 1)];
+      xp[e][jj] = inner ? a0 : (hb ? rb : 0.0);
+      xa[e][jj] = qn[Np + m];
+      xb[e][jj] = qn[2 * Np + m];
+    }
+  }
+  const int po = (tl < ntw ? es : (ntw * Pc - 1)) * 3 * Np;   // this pair in the stage
   double ps[RG];   // new p*_i at this lane's rows
 #pragma unroll
   for (int r = 0; r < RG; ++r) ps[r] = 0.0;
   if (P > 0) {
-    double xp[3][EK], xa[3][EK], xb[3][EK], xZ[3];
+    // the old residuals, loaded linearly now and staged after the MFMAs
+    double vr[KL];
 #pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      const bool inner = code[e] >= 0;
-      const int c = -1 - code[e];
-      const bool hb = !inner && (c & 3) == 0;
-      xZ[e] = L2.geo[(size_t)(inner ? code[e] : t) * 8 + 6];
-      const double* qn = b.q2o + ((size_t)(inner ? code[e] : t) * P + i) * 3 * Np;
-      const double* qbl = b.qb2 + (((size_t)(hb ? (c >> 3) : 0) * 2 + ((c >> 2) & 1)) * P + i) * Nfp;
-#pragma unroll
-      for (int jj = 0; jj < EK; ++jj) {
-        const int m = min(nn[e][jj], Np - 1);
-        xp[e][jj] = inner ? qn[m] : (hb ? qbl[min(nn[e][jj], Nfp - 1)] : 0.0);
-        xa[e][jj] = qn[Np + m];
-        xb[e][jj] = qn[2 * Np + m];
-      }
-    }
+    for (int k = 0; k < KL; ++k) vr[k] = b.res2[wbase + min(lane + 64 * k, cnt - 1)];
     const double* fj = sops + ta;
     const double* fl = sops + 2 * RG * RG * 16 + ta;
     const double Ki = Kb / (1.0 + sg[i]);
+    double vp[RG], va[RG], vb[RG];
+#pragma unroll
+    for (int j = 0; j < RG; ++j) {
+      const int n = min(4 * j + g, Np - 1);
+      vp[j] = sq[po + n];
+      va[j] = sq[po + Np + n];
+      vb[j] = sq[po + 2 * Np + n];
+    }
     // ---- volume: Dr p, Ds p and div v = Dr (grad r . v) + Ds (grad s . v)
     double Gr[RG], Gs[RG], rp[RG];
 #pragma unroll
@@ -178,7 +203,7 @@ __global__ void __launch_bounds__(kWaves2 * 64, 3) k_faces(LvlF F, Lvl2 L2, Face
       for (int jj = 0; jj < EK; ++jj) {
         const int kc = min(4 * jj + g, Nfp - 1);   // rows beyond Nfp: LIFT columns are 0
         const int a = smask[e * Nfp + kc];
-        const double pM = q[a], vnM = na * q[Np + a] + nb * q[2 * Np + a];
+        const double pM = sq[po + a], vnM = na * sq[po + Np + a] + nb * sq[po + 2 * Np + a];
         const double vnP = na * xa[e][jj] + nb * xb[e][jj];
         const double pG = inner ? xp[e][jj] : (dir ? -pM : (hb ? 2.0 * xp[e][jj] : 0.0));
         const double uG = inner ? vnP : (dir ? vnM : 0.0);
@@ -200,21 +225,23 @@ __global__ void __launch_bounds__(kWaves2 * 64, 3) k_faces(LvlF F, Lvl2 L2, Face
         }
       }
     }
-    // ---- LSRK update of the rows this lane holds
+#pragma unroll
+    for (int k = 0; k < KL; ++k)
+      if (lane + 64 * k < cnt) sr[lane + 64 * k] = vr[k];
+    // ---- LSRK update of the rows this lane holds, into the stage
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
-      const int n = 4 * r + g;
-      const double r0 = A * ro[r][0] + dt * rp[r];
-      const double r1 = A * ro[r][1] + dt * (-irho * (rx * Gr[r] + sx * Gs[r]));
-      const double r2 = A * ro[r][2] + dt * (-irho * (ry * Gr[r] + sy * Gs[r]));
+      const int n = 4 * r + g, nc = min(n, Np - 1);
+      const double r0 = A * sr[po + nc] + dt * rp[r];
+      const double r1 = A * sr[po + Np + nc] + dt * (-irho * (rx * Gr[r] + sx * Gs[r]));
+      const double r2 = A * sr[po + 2 * Np + nc] + dt * (-irho * (ry * Gr[r] + sy * Gs[r]));
       ps[r] = vp[r] - S0[r] + B * r0;
       if (col && n < Np) {
-        double* rw = b.res2 + pb + n;
-        rw[0] = r0;
-        rw[Np] = r1;
-        rw[2 * Np] = r2;
-        b.q2n[pb + Np + n] = va[r] + B * r1;
-        b.q2n[pb + 2 * Np + n] = vb[r] + B * r2;
+        sr[po + n] = r0;
+        sr[po + Np + n] = r1;
+        sr[po + 2 * Np + n] = r2;
+        sq[po + Np + n] = va[r] + B * r1;
+        sq[po + 2 * Np + n] = vb[r] + B * r2;
       }
     }
   }
@@ -233,7 +260,18 @@ __global__ void __launch_bounds__(kWaves2 * 64, 3) k_faces(LvlF F, Lvl2 L2, Face
         b.qb3[(size_t)t * Np + n] = rm;
         b.q03[(size_t)t * Np + n] = S;
       }
-      if (P > 0) b.q2n[pb + n] = ps[r] + S;
+      if (P > 0) sq[po + n] = ps[r] + S;
+    }
+  }
+  // ---- linear stores of the new q2 and res2 of the wave's pairs
+  if (P > 0) {
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const int x = lane + 64 * k;
+      if (x < cnt) {
+        b.q2n[wbase + x] = sq[x];
+        b.res2[wbase + x] = sr[x];
+      }
     }
   }
 }
