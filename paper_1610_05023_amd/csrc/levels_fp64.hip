@@ -59,8 +59,13 @@ __device__ __forceinline__ Rsrc rsrc(const void* p, unsigned bytes) {
 __device__ __forceinline__ double bld(Rsrc r, unsigned voff, unsigned soff) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
-__device__ __forceinline__ void bst(Rsrc r, unsigned voff, unsigned soff, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+// streaming load/store (non-temporal: read or written once per stage, so
+// they leave the L2 to the state that is re-read within the stage)
+__device__ __forceinline__ double bldn(Rsrc r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 2));
+}
+__device__ __forceinline__ void bstn(Rsrc r, unsigned voff, unsigned soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 2);
 }
 
 template <int N>
@@ -309,7 +314,7 @@ __device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restric
         const unsigned o = tb + (unsigned)min(4 * (i0 + ii) + g, Np - 1) * (kTile * 8);
 #pragma unroll
         for (int fl = 0; fl < 4; ++fl) {
-          ro[ii][fl] = (i0 + ii < RG) ? bld(Rr, o, fl * FS) : 0.0;
+          ro[ii][fl] = (i0 + ii < RG) ? bldn(Rr, o, fl * FS) : 0.0;
           qo_[ii][fl] = (i0 + ii < RG) ? bld(Rq, o, fl * FS) : 0.0;
         }
       }
@@ -330,8 +335,8 @@ __device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restric
 #pragma unroll
           for (int fl = 0; fl < 4; ++fl) {
             const double rr = A * ro[ii][fl] + dt * rhs[fl];
-            bst(Rr, o, fl * FS, rr);
-            bst(Rn, o, fl * FS, qo_[ii][fl] + B * rr);
+            bstn(Rr, o, fl * FS, rr);
+            bstn(Rn, o, fl * FS, qo_[ii][fl] + B * rr);
           }
         }
       }
