@@ -36,6 +36,33 @@ def bytes_per_tet_stage(Np):
     return 16 * Np * 8 + 27 * 8 + 20
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_level3_layered40_traffic.txt")
+KERNEL3_SOURCES = ["levels_fp64.hip", "kernels.hpp", "levels.hpp"]
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the 3D kernel on the 40^3 workload, from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the
+    calibration recorded there); None once the kernel sources differ from
+    the ones the counters were taken with."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(TRAFFIC_PROFILE).read().splitlines():
+            key, sep, val = line.partition(": ")
+            if sep and key in ("traffic_bytes_per_launch_k_level3", "source_sha256"):
+                fields[key] = val.strip()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL3_SOURCES:
+        with open(os.path.join(ROOT, "paper_1610_05023_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("source_sha256") != h.hexdigest() or "traffic_bytes_per_launch_k_level3" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch_k_level3"])
+
+
 def achieved_gbs(alg_bytes, avg_ms):
     return alg_bytes / (avg_ms * 1e-3) / 1e9
 
@@ -69,7 +96,7 @@ def build_batch_workload(n=20, N=4, P=3, shots=64):
 def cpu_baseline(seconds_target=20.0):
     """The FP64 oracle (numpy, as is) on a bounded sample of the workload:
     the same medium recipe, degree and HABC order on a 20^3 x 6 = 48,000-tet
-    mesh, stepped for 2 steps (10 RK stages).  Per-element work is the same
+    mesh, stepped for 10 steps (50 RK stages, about 10 s).  Per-element work is the same
     as on the 40^3 mesh, so DOF-updates/s per stage carries over."""
     import numpy as np
     import workloads as w
@@ -79,7 +106,7 @@ def cpu_baseline(seconds_target=20.0):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = 1
-    n, N, P, steps = 20, 4, 6, 2
+    n, N, P, steps = 20, 4, 6, 10
     VX, E = w.kuhn_mesh(n)
     rho, c, *_ = w.layered_medium(n, seed=2)
     o = Oracle(VX, E, N, P, rho, c)
@@ -173,6 +200,7 @@ def main():
     print(f"[bench] {args.steps} steps in {el:.3f} s; 3D kernel avg {avg3_ms * 1e3:.1f} us over "
           f"{n3} launches; {achieved_gbs(alg, avg3_ms):.0f} GB/s; check={finite}",
           file=sys.stderr, flush=True)
+    traffic = profiled_traffic() if (not batch and args.n == 40) else None
     cpu = None
     if not args.no_cpu_baseline and not batch:
         try:
@@ -204,7 +232,9 @@ def main():
                    "N": wl["N"], "P": wl["P"], "unknowns": U, "dt": dt,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
                      "kernel": "k_level3 (3D volume + surface + LSRK update)",
                      "avg_us": avg3_ms * 1e3, "alg_bytes_per_launch": alg},
         "cpu_baseline": cpu,
