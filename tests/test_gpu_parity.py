@@ -164,3 +164,14 @@ def test_degrees_and_habc_orders(N, P):
     (two edge nodes per thread) on all-HABC faces, every array random."""
     case = make_case(n=3, N=N, P=P, init="random", seed=90 + 7 * N + P)
     _check(case, 4, 1e-3)
+
+
+def test_full_size_layered_one_step():
+    """The bench workload at full size (40^3 x 6 tets, N = 4, P = 6, layered
+    medium, Ricker source) in the bench's launch configuration: one step
+    from a random state of every array, every array compared with the
+    oracle (about a minute of oracle time)."""
+    n = 40
+    case = make_case(n=n, N=4, P=6, medium="layered", init="random", seed=123,
+                     source=((0.5 + 0.3 / n, 0.5 + 0.2 / n, 0.5 + 0.1 / n), 80.0, 0.0125))
+    _check(case, 1, w.kuhn_dt(n, 4, 3.0), t0=0.01)
