@@ -29,11 +29,11 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, nominal
 METRIC = "DOF-updates/s per RK stage (FP64 vs mixed/batched) + fraction of HBM roofline"
 
 
-def bytes_per_tet_stage(Np):
+def bytes_per_tet_stage(Np, word=8):
     """Algorithmic HBM bytes of the 3D level per tet per stage: q and res read
-    and written (16 Np words of 8 bytes), 27 per-tet constants, 20 bytes of
-    connectivity."""
-    return 16 * Np * 8 + 27 * 8 + 20
+    and written (16 Np words of `word` bytes), 27 per-tet FP64 constants, 20
+    bytes of connectivity."""
+    return 16 * Np * word + 27 * 8 + 20
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_level3_layered40_traffic.txt")
@@ -138,6 +138,10 @@ def main():
                     help="layered: the 40^3 layered-medium step (default); batch: 64 shots "
                          "on a 20^3 mesh stepped together")
     ap.add_argument("--shots", type=int, default=64)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="fp32: FP32 3D level on FP32 MFMA, FP64 boundary levels")
+    ap.add_argument("--order", type=int, default=None, help="override the degree N")
+    ap.add_argument("--habc", type=int, default=None, help="override the HABC order P")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run 1 GiB reference kernels first (for PMC byte counters)")
     args = ap.parse_args()
@@ -167,10 +171,16 @@ def main():
     else:
         wl = build_workload(n=args.n)
         nsh = 1
+    if args.order is not None:
+        wl["N"] = args.order
+        wl["dt"] = __import__("workloads").kuhn_dt(wl["n"], wl["N"], float(wl["c"].max()))
+    if args.habc is not None:
+        wl["P"] = args.habc
     K = wl["E"].shape[0]
     t_setup = time.perf_counter()
+    prec = 2 if args.precision == "fp32" else 0
     s = Solver(wl["VX"], wl["E"], wl["N"], wl["P"], wl["rho"], wl["c"], device=0,
-               n_shots=nsh).bind()
+               n_shots=nsh, precision=prec).bind()
     if batch:
         for j in range(nsh):
             s.set_source(wl["xs"][j], wl["f0"], wl["t0"], shot=j)
@@ -195,12 +205,14 @@ def main():
     value = U * 5 * args.steps / el
     avg3_ms = ms3 / max(n3, 1)
     # per-tet constants are read once per shot in this kernel
-    alg = bytes_per_tet_stage(k["Np"]) * K * nsh
+    alg = bytes_per_tet_stage(k["Np"], 4 if prec else 8) * K * nsh
     achieved = achieved_gbs(alg, avg3_ms)
     print(f"[bench] {args.steps} steps in {el:.3f} s; 3D kernel avg {avg3_ms * 1e3:.1f} us over "
           f"{n3} launches; {achieved_gbs(alg, avg3_ms):.0f} GB/s; check={finite}",
           file=sys.stderr, flush=True)
-    traffic = profiled_traffic() if (not batch and args.n == 40) else None
+    default_cfg = (not batch and args.n == 40 and prec == 0 and args.order is None
+                   and args.habc is None)
+    traffic = profiled_traffic() if default_cfg else None
     cpu = None
     if not args.no_cpu_baseline and not batch:
         try:
@@ -218,15 +230,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == 0 else "f32 (3D level) + f64 (boundary levels)",
         "data": "synthetic",
-        "config": ({"workload": f"FP64 DG+HABC step, {args.n}^3 x 6 = {K}-tet Kuhn mesh of the "
-                                f"unit cube, N=4 (Np=35), HABC P=6 with edges and corners, 5 "
-                                f"random layers (seed 2), Ricker point source"}
+        "config": ({"workload": f"{'FP64' if prec == 0 else 'FP32-3D'} DG+HABC step, {args.n}^3 x 6 "
+                                f"= {K}-tet Kuhn mesh of the unit cube, N={wl['N']}, HABC "
+                                f"P={wl['P']} with edges and corners, 5 random layers (seed 2), "
+                                f"Ricker point source"}
                    if not batch else
-                   {"workload": f"FP64 DG+HABC step, {nsh} shots stepped together on a "
-                                f"{wl['n']}^3 x 6 = {K}-tet Kuhn mesh, N={wl['N']}, HABC "
-                                f"P={wl['P']}, rho=c=1, one Ricker source per shot (seed 4)",
+                   {"workload": f"{'FP64' if prec == 0 else 'FP32-3D'} DG+HABC step, {nsh} shots "
+                                f"stepped together on a {wl['n']}^3 x 6 = {K}-tet Kuhn mesh, "
+                                f"N={wl['N']}, HABC P={wl['P']}, rho=c=1, one Ricker source per "
+                                f"shot (seed 4)",
                     "shots": nsh}) | {
                    "K_tet": K, "K_tri": k["Ktri"], "K_lin": k["Klin"], "K_pnt": k["Kpnt"],
                    "N": wl["N"], "P": wl["P"], "unknowns": U, "dt": dt,

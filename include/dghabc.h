@@ -56,7 +56,13 @@ typedef enum {
   DGH_EUNSTABLE = -6   /* energy growth found by dgh_check */
 } dgh_status;
 
-typedef enum { DGH_FP64 = 0 } dgh_precision;
+/* Arithmetic of the 3D level (Section 3.2's volume, surface and update):
+ * DGH_FP64, or DGH_FP32_MFMA: FP32 3D state and residual with the volume
+ * and LIFT contractions on the FP32 MFMA (FP32 accumulation).  The face,
+ * edge and corner levels, their RK accumulation and the energy stay FP64 in
+ * both.  The FP32 variant's results differ from FP64 by rounding only; its
+ * error is reported by the tests, not bounded by the FP64 parity target. */
+typedef enum { DGH_FP64 = 0, DGH_FP32_MFMA = 2 } dgh_precision;
 
 /* Boundary condition of a face of the cuboid (faces x-, x+, y-, y+, z-, z+).
  * HABC: Pade HABC of order P (Section 2), with edge/corner compatibility where
@@ -77,7 +83,8 @@ enum {
   DGH_C_P, DGH_C_N, DGH_C_NSHOTS, DGH_NCOUNTS
 };
 
-/* Creates a context for HIP device `device`.  precision: DGH_FP64.
+/* Creates a context for HIP device `device`.  precision: DGH_FP64 or
+ * DGH_FP32_MFMA (dgh_precision).
  * n_shots (1..4096): independent problems on the same mesh and medium,
  * each with its own state and point source, stepped together: every launch
  * covers all shots (the operators, geometry and maps are shared).  Each

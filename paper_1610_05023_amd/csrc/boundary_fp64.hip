@@ -73,7 +73,6 @@ __global__ void __launch_bounds__(512, 4) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, L
     b.res2 += k * sh.st2;
     b.qb3 += k * sh.stb3;
     b.q03 += k * sh.stb3;
-    b.q3n += k * sh.st3;
     b.q1o += k * sh.st1;
     b.q1n += k * sh.st1;
     b.res1 += k * sh.st1;

@@ -10,12 +10,19 @@ namespace {
 
 __global__ void __launch_bounds__(256) k_nonfinite(ScanList s, int* __restrict__ flags) {
   const int a = blockIdx.y;
-  const double* __restrict__ p = s.ptr[a];
   const size_t n = s.n[a];
   int bad = 0;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    bad |= !isfinite(p[i]);
+  if (s.f32[a]) {
+    const float* __restrict__ p = static_cast<const float*>(s.ptr[a]);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+      bad |= !isfinite(p[i]);
+  } else {
+    const double* __restrict__ p = static_cast<const double*>(s.ptr[a]);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+      bad |= !isfinite(p[i]);
+  }
   bad = __syncthreads_or(bad);
   if (threadIdx.x == 0) flags[a * gridDim.x + blockIdx.x] = bad;
 }

@@ -34,12 +34,13 @@ struct Region {
 
 struct Layout {
   size_t total = 0;
-  Region q3[2], res3, geo3, zn3, nbr3, ops3, fmask3, fmap3, mass3, J3, esum;
+  Region q3[2], res3, geo3, zn3, nbr3, ops3, ops3f, fmask3, fmap3, mass3, J3, esum;
   Region q2[2], res2, qb3, q03, geo2, info2, tetnode2, nbrnode2, ops2, fmask2, gamma;
   Region q1[2], res1, qb2, q02, geo1, info1, trinode1, ops1, cji, cij, G, H;
   Region qb1, info0, nrm0, T, srcw, srcp, wlines, wcorners, flags, ops2f;
   // per-shot strides (doubles) of the state arrays
   size_t st3 = 0, st2 = 0, stb3 = 0, st1 = 0, stb2 = 0, stb1 = 0;
+  size_t e3 = 8;   // bytes per element of the 3D state (8 FP64, 4 FP32)
   Region* add(Region& r, size_t bytes) {
     r.off = total;
     r.bytes = bytes;
@@ -108,6 +109,7 @@ T* dptr(dgh_ctx* c, const Region& r) {
 // Builds the device-layout arrays on the host.
 struct HostArrays {
   std::vector<double> geo3, zn3, ops3, mass3, J3, ops2f;
+  std::vector<float> ops3f;
   std::vector<int> nbr3, fmask3, fmap3;
   std::vector<double> geo2, ops2;
   std::vector<int> info2, tetnode2, nbrnode2, fmask2;
@@ -255,6 +257,30 @@ void build_host_arrays(dgh_ctx* c, HostArrays& h) {
                   m.tet.LIFT[row * 4 * Nfp + f * Nfp + k];
           }
   }
+  if (c->precision == DGH_FP32_MFMA) {
+    // A-fragments of the FP32 16x16x4 MFMA (see Lvl3::ops32)
+    const int RG = (Np + 3) / 4, RB = (Np + 15) / 16, FK = (Nfp + 3) / 4;
+    h.ops3f.assign(dgh::frag3f_size(m.N), 0.0f);
+    const dgh::Mat* Ds[3] = {&m.tet.Dr, &m.tet.Ds, &m.tet.Dt};
+    for (int d = 0; d < 3; ++d)
+      for (int rb = 0; rb < RB; ++rb)
+        for (int j = 0; j < RG; ++j)
+          for (int l = 0; l < 64; ++l) {
+            const int row = 16 * rb + l % 16, col = 4 * j + l / 16;
+            if (row < Np && col < Np)
+              h.ops3f[(((size_t)d * RB + rb) * RG + j) * 64 + l] = (float)(*Ds[d])[row * Np + col];
+          }
+    const size_t off = (size_t)3 * RB * RG * 64;
+    for (int rb = 0; rb < RB; ++rb)
+      for (int f = 0; f < 4; ++f)
+        for (int jj = 0; jj < FK; ++jj)
+          for (int l = 0; l < 64; ++l) {
+            const int row = 16 * rb + l % 16, k = 4 * jj + l / 16;
+            if (row < Np && k < Nfp)
+              h.ops3f[off + (((size_t)rb * 4 + f) * FK + jj) * 64 + l] =
+                  (float)m.tet.LIFT[row * 4 * Nfp + f * Nfp + k];
+          }
+  }
   h.mass3 = m.tet.Mass;
   h.fmask3 = m.tet.Fmask;
   h.fmap3 = m.fmap;
@@ -386,7 +412,8 @@ void compute_layout(dgh_ctx* c) {
   const size_t d = sizeof(double), i4 = sizeof(int), S = (size_t)c->n_shots;
   // every state array holds n_shots shots, each starting 256-byte aligned
   const int Kt = m.Ktri, Np2 = m.tri.Np, Nfp2 = m.tri.Nfp, Kl = m.Klin, Np1 = m.line.Np;
-  L.st3 = round32((size_t)nt * 4 * Np * T);
+  L.e3 = c->precision == DGH_FP32_MFMA ? 4 : 8;
+  L.st3 = ((size_t)nt * 4 * Np * T + 63) / 64 * 64;   // 256-byte aligned shots
   // at least one set of one triangle (read, unused, by the face kernel at P = 0)
   L.st2 = round32((size_t)Kt * std::max(P, 1) * 3 * Np2);
   L.stb3 = round32(std::max<size_t>(Nfp, (size_t)Kt * Np2));  // >= one triangle (read masked)
@@ -394,13 +421,14 @@ void compute_layout(dgh_ctx* c) {
   // at least one line, so that the face kernel may read line 0 of qb2
   L.stb2 = round32((size_t)std::max(Kl, 1) * 2 * std::max(P, 1) * Np1);
   L.stb1 = round32((size_t)m.Kpnt * 3 * P * P);
-  L.add(L.q3[0], S * L.st3 * d);
-  L.add(L.q3[1], S * L.st3 * d);
-  L.add(L.res3, S * L.st3 * d);
+  L.add(L.q3[0], S * L.st3 * L.e3);
+  L.add(L.q3[1], S * L.st3 * L.e3);
+  L.add(L.res3, S * L.st3 * L.e3);
   L.add(L.geo3, (size_t)nt * 12 * T * d);
   L.add(L.zn3, (size_t)nt * 4 * T * d);
   L.add(L.nbr3, (size_t)nt * 4 * T * i4);
   L.add(L.ops3, (size_t)dgh::frag3_size(m.N) * d);
+  L.add(L.ops3f, L.e3 == 4 ? (size_t)dgh::frag3f_size(m.N) * sizeof(float) : 1);
   L.add(L.fmask3, (size_t)4 * Nfp * i4);
   L.add(L.fmap3, (size_t)96 * Nfp * i4);
   L.add(L.mass3, (size_t)Np * Np * d);
@@ -463,6 +491,7 @@ void fill_levels(dgh_ctx* c) {
   a.Nfp = m.tet.Nfp;
   a.nqb3 = std::max(m.tet.Nfp, m.Ktri * m.tri.Np);
   a.ops = dptr<double>(c, L.ops3);
+  a.ops32 = dptr<float>(c, L.ops3f);
   a.fmask = dptr<int>(c, L.fmask3);
   a.fmap = dptr<int>(c, L.fmap3);
   a.geo = dptr<double>(c, L.geo3);
@@ -539,7 +568,9 @@ extern "C" {
 dgh_status dgh_create(dgh_ctx** out, int device, int precision, int n_shots) {
   if (!out) return DGH_EINVAL;
   *out = nullptr;
-  if (precision != DGH_FP64 || n_shots < 1 || n_shots > 4096 || device < 0) return DGH_EINVAL;
+  if ((precision != DGH_FP64 && precision != DGH_FP32_MFMA) || n_shots < 1 || n_shots > 4096 ||
+      device < 0)
+    return DGH_EINVAL;
   dgh_ctx* c = new (std::nothrow) dgh_ctx();
   if (!c) return DGH_ENOMEM;
   c->device = device;
@@ -653,7 +684,7 @@ dgh_status dgh_workspace_size(dgh_ctx* c, size_t* bytes) {
   if (!c || !bytes) return DGH_EINVAL;
   if (c->stage < S_MATERIAL) return fail(c, DGH_ESTATE, "workspace_size before set_material");
   compute_layout(c);
-  if (c->lay.st3 * sizeof(double) > 0xffffffffull)
+  if (c->lay.st3 * c->lay.e3 > 0xffffffffull)
     return fail(c, DGH_EINVAL, "3D state of a shot exceeds 4 GiB (32-bit buffer offsets)");
   *bytes = c->lay.total;
   return DGH_OK;
@@ -663,7 +694,7 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
   if (!c) return DGH_EINVAL;
   if (c->stage < S_MATERIAL) return fail(c, DGH_ESTATE, "bind before set_material");
   compute_layout(c);
-  if (c->lay.st3 * sizeof(double) > 0xffffffffull)
+  if (c->lay.st3 * c->lay.e3 > 0xffffffffull)
     return fail(c, DGH_EINVAL, "3D state of a shot exceeds 4 GiB (32-bit buffer offsets)");
   if (!dev || bytes < c->lay.total) return fail(c, DGH_ENOMEM, "workspace too small");
   if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(c, DGH_EINVAL, "workspace not 256-byte aligned");
@@ -680,6 +711,7 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
   HIPCHECK(c, upload(c, L.zn3, h.zn3));
   HIPCHECK(c, upload(c, L.nbr3, h.nbr3));
   HIPCHECK(c, upload(c, L.ops3, h.ops3));
+  HIPCHECK(c, upload(c, L.ops3f, h.ops3f));
   HIPCHECK(c, upload(c, L.fmask3, h.fmask3));
   HIPCHECK(c, upload(c, L.fmap3, h.fmap3));
   HIPCHECK(c, upload(c, L.mass3, h.mass3));
@@ -737,8 +769,13 @@ dgh_status dgh_set_state(dgh_ctx* c, int shot, const double* const* arr) {
     const double* src = (arr && arr[which]) ? arr[which] : zero.data();
     to_tiles(src, buf.data(), c->slot2elem, Np);
     const Region& r = which == DGH_Q3 ? L.q3[cur] : L.res3;
-    HIPCHECK(c, hipMemcpy(c->ws + r.off + shot * L.st3 * sizeof(double), buf.data(),
-                          buf.size() * sizeof(double), hipMemcpyHostToDevice));
+    char* dst = c->ws + r.off + shot * L.st3 * L.e3;
+    if (L.e3 == 4) {   // FP32 state: rounded on upload
+      std::vector<float> f(buf.begin(), buf.end());
+      HIPCHECK(c, hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+      HIPCHECK(c, hipMemcpy(dst, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
   }
   struct Item { int idx; const Region* r; size_t n, stride; };
   const int P = c->P;
@@ -778,8 +815,14 @@ dgh_status dgh_read_fields(dgh_ctx* c, int shot, double* const* arr) {
   for (int which : {DGH_Q3, DGH_RES3}) {
     if (!arr[which]) continue;
     const Region& r = which == DGH_Q3 ? L.q3[cur] : L.res3;
-    HIPCHECK(c, hipMemcpy(buf.data(), c->ws + r.off + shot * L.st3 * sizeof(double),
-                          buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+    const char* src = c->ws + r.off + shot * L.st3 * L.e3;
+    if (L.e3 == 4) {
+      std::vector<float> f(buf.size());
+      HIPCHECK(c, hipMemcpy(f.data(), src, f.size() * sizeof(float), hipMemcpyDeviceToHost));
+      std::copy(f.begin(), f.end(), buf.begin());
+    } else {
+      HIPCHECK(c, hipMemcpy(buf.data(), src, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+    }
     from_tiles(buf.data(), arr[which], c->slot2elem, Np);
   }
   struct Item { int idx; const Region* r; size_t n, stride; };
@@ -872,9 +915,14 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
         }
         HIPCHECK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
       }
-      HIPCHECK(c, dgh::launch_level3(c->L3, dptr<double>(c, L.q3[o]), dptr<double>(c, L.q3[n]),
-                                     dptr<double>(c, L.res3), dptr<double>(c, L.qb3), kA[s], kB[s],
-                                     dt, sh, c->stream));
+      if (L.e3 == 4)
+        HIPCHECK(c, dgh::launch_level3_f32(c->L3, dptr<float>(c, L.q3[o]), dptr<float>(c, L.q3[n]),
+                                           dptr<float>(c, L.res3), dptr<double>(c, L.qb3), kA[s],
+                                           kB[s], dt, sh, c->stream));
+      else
+        HIPCHECK(c, dgh::launch_level3(c->L3, dptr<double>(c, L.q3[o]), dptr<double>(c, L.q3[n]),
+                                       dptr<double>(c, L.res3), dptr<double>(c, L.qb3), kA[s],
+                                       kB[s], dt, sh, c->stream));
       if (c->timing) {
         HIPCHECK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
@@ -882,8 +930,8 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
       {
         const dgh::FaceBufs fb{dptr<double>(c, L.q2[o]), dptr<double>(c, L.q2[n]),
                                dptr<double>(c, L.res2), dptr<double>(c, L.qb3),
-                               dptr<double>(c, L.q03), dptr<double>(c, L.q3[n]),
-                               dptr<double>(c, L.qb2)};
+                               dptr<double>(c, L.q03), c->ws + L.q3[n].off,
+                               dptr<double>(c, L.qb2), L.e3 == 4 ? 1 : 0};
         HIPCHECK(c, dgh::launch_faces(c->LF, c->L2, fb, sh, kA[s], kB[s], dt, c->stream));
       }
       HIPCHECK(c, dgh::launch_boundary(c->LB, c->L2, c->L1, c->L0, c->L3, dptr<double>(c, L.q2[o]),
@@ -904,8 +952,8 @@ dgh_status dgh_energy(dgh_ctx* c, int shot, double* e) {
   if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "energy before bind");
   if (shot < 0 || shot >= c->n_shots) return fail(c, DGH_EINVAL, "shot out of range");
   const Layout& L = c->lay;
-  HIPCHECK(c, dgh::launch_energy(c->L3, dptr<double>(c, L.q3[c->cur]) + shot * L.st3,
-                                 dptr<double>(c, L.mass3),
+  HIPCHECK(c, dgh::launch_energy(c->L3, c->ws + L.q3[c->cur].off + shot * L.st3 * L.e3,
+                                 L.e3 == 4 ? 1 : 0, dptr<double>(c, L.mass3),
                                  dptr<double>(c, L.J3), dptr<double>(c, L.esum), c->stream));
   std::vector<double> part(c->ntile);
   HIPCHECK(c, hipMemcpyAsync(part.data(), c->ws + L.esum.off, c->ntile * sizeof(double),
@@ -940,7 +988,9 @@ dgh_status dgh_check(dgh_ctx* c, int shot, double e_ref, double rel_tol, double*
   dgh::ScanList sl{};
   for (int a = 0; a < DGH_NARRAYS; ++a)
     if (ns[a] > 0) {
-      sl.ptr[sl.count] = dptr<double>(c, *regs[a]) + shot * strides[a];
+      const size_t eb = a < 2 ? L.e3 : sizeof(double);
+      sl.ptr[sl.count] = c->ws + regs[a]->off + shot * strides[a] * eb;
+      sl.f32[sl.count] = eb == 4 ? 1 : 0;
       sl.n[sl.count] = ns[a];
       ++sl.count;
     }

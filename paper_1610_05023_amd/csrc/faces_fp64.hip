@@ -34,7 +34,8 @@ struct Dims2 {
   static constexpr int NFRAG = 2 * RG * RG + RG * 3 * EK;
 };
 
-template <int N>
+// T3: type of the 3D state (double, or float for the FP32 3D variant).
+template <int N, class T3>
 __global__ void __launch_bounds__(kWaves2 * 64, 2) k_faces(LvlF F, Lvl2 L2, FaceBufs b, Shots sh,
                                                            double A, double B, double dt) {
   using D = Dims2<N>;
@@ -57,7 +58,7 @@ __global__ void __launch_bounds__(kWaves2 * 64, 2) k_faces(LvlF F, Lvl2 L2, Face
     b.res2 += k * sh.st2;
     b.qb3 += k * sh.stb3;
     b.q03 += k * sh.stb3;
-    b.q3n += k * sh.st3;
+    b.q3n = static_cast<const T3*>(b.q3n) + k * sh.st3;
     b.qb2 += k * sh.stb2;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -110,11 +111,11 @@ __global__ void __launch_bounds__(kWaves2 * 64, 2) k_faces(LvlF F, Lvl2 L2, Face
   // ---- loads through the maps: new 3D trace, exterior values of the edges
   double p3[RG], u3[RG];
   {
-    const double* q3 = b.q3n + (size_t)(e3 >> 4) * 4 * F.np3 * kTile + (e3 & 15);
+    const T3* q3 = static_cast<const T3*>(b.q3n) + (size_t)(e3 >> 4) * 4 * F.np3 * kTile + (e3 & 15);
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
-      p3[r] = q3[n3[r] * kTile];
-      u3[r] = q3[((1 + ax) * F.np3 + n3[r]) * kTile];
+      p3[r] = (double)q3[n3[r] * kTile];
+      u3[r] = (double)q3[((1 + ax) * F.np3 + n3[r]) * kTile];
     }
   }
   // every load is issued at an address valid for any edge kind (own
@@ -276,6 +277,16 @@ __global__ void __launch_bounds__(kWaves2 * 64, 2) k_faces(LvlF F, Lvl2 L2, Face
   }
 }
 
+template <int N>
+hipError_t launch_faces_n(const LvlF& F, const Lvl2& L2, const FaceBufs& b, const Shots& sh,
+                          double A, double B, double dt, dim3 grid, dim3 block, hipStream_t st) {
+  if (b.q3f32)
+    hipLaunchKernelGGL((k_faces<N, float>), grid, block, 0, st, F, L2, b, sh, A, B, dt);
+  else
+    hipLaunchKernelGGL((k_faces<N, double>), grid, block, 0, st, F, L2, b, sh, A, B, dt);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_faces(const LvlF& F, const Lvl2& L2, const FaceBufs& b, const Shots& sh,
@@ -286,15 +297,14 @@ hipError_t launch_faces(const LvlF& F, const Lvl2& L2, const FaceBufs& b, const 
   const int waves = (L2.Kt + TW - 1) / TW;
   const dim3 grid((waves + kWaves2 - 1) / kWaves2, sh.n), block(kWaves2 * 64);
   switch (L2.Np) {
-    case 3: hipLaunchKernelGGL(k_faces<1>, grid, block, 0, st, F, L2, b, sh, A, B, dt); break;
-    case 6: hipLaunchKernelGGL(k_faces<2>, grid, block, 0, st, F, L2, b, sh, A, B, dt); break;
-    case 10: hipLaunchKernelGGL(k_faces<3>, grid, block, 0, st, F, L2, b, sh, A, B, dt); break;
-    case 15: hipLaunchKernelGGL(k_faces<4>, grid, block, 0, st, F, L2, b, sh, A, B, dt); break;
-    case 21: hipLaunchKernelGGL(k_faces<5>, grid, block, 0, st, F, L2, b, sh, A, B, dt); break;
-    case 28: hipLaunchKernelGGL(k_faces<6>, grid, block, 0, st, F, L2, b, sh, A, B, dt); break;
+    case 3: return launch_faces_n<1>(F, L2, b, sh, A, B, dt, grid, block, st);
+    case 6: return launch_faces_n<2>(F, L2, b, sh, A, B, dt, grid, block, st);
+    case 10: return launch_faces_n<3>(F, L2, b, sh, A, B, dt, grid, block, st);
+    case 15: return launch_faces_n<4>(F, L2, b, sh, A, B, dt, grid, block, st);
+    case 21: return launch_faces_n<5>(F, L2, b, sh, A, B, dt, grid, block, st);
+    case 28: return launch_faces_n<6>(F, L2, b, sh, A, B, dt, grid, block, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace dgh

@@ -8,6 +8,13 @@ namespace dgh {
 
 constexpr int kTile = 16;  // elements per tile of the 3D node-major layout
 
+// Number of floats of the FP32 3D operator fragments for degree N.
+inline int frag3f_size(int N) {
+  const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
+  const int RG = (Np + 3) / 4, RB = (Np + 15) / 16, FK = (Nfp + 3) / 4;
+  return (3 * RB * RG + RB * 4 * FK) * 64;
+}
+
 // Number of doubles of the 3D operator fragments for degree N.
 inline int frag3_size(int N) {
   const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
@@ -30,6 +37,11 @@ struct Lvl3 {
   // [RG][4 faces][FK][16] with entry t holding LIFT[4 rg + i][f Nfp + 4 jj + k];
   // zero outside the matrix.  RG = ceil(Np/4), FK = ceil(Nfp/4).
   const double* ops;
+  // FP32 variant: A-fragments of the FP32 16x16x4 MFMA, Dr, Ds, Dt as
+  // [3][RB][RG][64] with lane l holding D[16 rb + l%16][4 j + l/16], then
+  // LIFT as [RB][4][FK][64] with lane l holding LIFT[16 rb + l%16][f Nfp +
+  // 4 jj + l/16]; zero outside the matrix.  RB = ceil(Np/16).
+  const float* ops32;
   const int* fmask;    // 4 x Nfp
   const int* fmap;     // 4 x 4 x 6 x Nfp
   const double* geo;
@@ -103,6 +115,10 @@ struct Shots {
 hipError_t launch_level3(const Lvl3& L, const double* qo, double* qn, double* res,
                          const double* qb3, double A, double B, double dt, const Shots& sh,
                          hipStream_t st);
+// FP32 state, FP32 MFMA (levels_fp32.hip); qb3 and the rest of the step FP64.
+hipError_t launch_level3_f32(const Lvl3& L, const float* qo, float* qn, float* res,
+                             const double* qb3, double A, double B, double dt, const Shots& sh,
+                             hipStream_t st);
 // Work list of the line-group kernel: block b updates the lines
 // lines[b][*] (each with its edge system), then the corners corners[b][*];
 // -1 ends a list.  A block holds every line of its corners.
@@ -129,8 +145,9 @@ struct LvlF {
 struct FaceBufs {
   const double* q2o;
   double *q2n, *res2, *qb3, *q03;
-  const double* q3n;
+  const void* q3n;     // new 3D state: double, or float for the FP32 variant
   const double* qb2;
+  int q3f32;           // 1 if q3n holds floats
 };
 hipError_t launch_faces(const LvlF& F, const Lvl2& L2, const FaceBufs& b, const Shots& sh,
                         double A, double B, double dt, hipStream_t st);
@@ -144,14 +161,16 @@ inline int frag2_size(int N) {
 constexpr int kScanMax = 12;
 constexpr int kScanBlocks = 256;
 struct ScanList {
-  const double* ptr[kScanMax];
+  const void* ptr[kScanMax];
   size_t n[kScanMax];
+  int f32[kScanMax];   // 1: the array holds floats, 0: doubles
   int count;
 };
 hipError_t launch_nonfinite(const ScanList& s, int* flags, hipStream_t st);
 
-// FP64 energy partial sums: one value per tile written to out[ntile].
-hipError_t launch_energy(const Lvl3& L, const double* q, const double* mass, const double* J,
-                         double* out, hipStream_t st);
+// FP64 energy partial sums: one value per tile written to out[ntile]; q
+// holds doubles, or floats if q_f32.
+hipError_t launch_energy(const Lvl3& L, const void* q, int q_f32, const double* mass,
+                         const double* J, double* out, hipStream_t st);
 
 }  // namespace dgh

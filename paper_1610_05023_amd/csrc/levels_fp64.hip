@@ -345,8 +345,10 @@ __device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restric
 }
 
 // -------------------------------------------------------------- energy ---
-// One block per tile; partial sum of J/2 (p M p / (rho c^2) + rho u M u).
-__global__ void k_energy(Lvl3 L, const double* __restrict__ q, const double* __restrict__ mass,
+// One block per tile; partial sum of J/2 (p M p / (rho c^2) + rho u M u),
+// accumulated in FP64 whatever the state's type.
+template <class T>
+__global__ void k_energy(Lvl3 L, const T* __restrict__ q, const double* __restrict__ mass,
                          const double* __restrict__ J, double* __restrict__ out) {
   const int Np = L.Np, tile = blockIdx.x, tid = threadIdx.x, es = tid & 15, g = tid >> 4;
   const int e = tile * kTile + es;
@@ -355,17 +357,17 @@ __global__ void k_energy(Lvl3 L, const double* __restrict__ q, const double* __r
   const double* gt = L.geo + (size_t)tile * 12 * kTile + es;
   const double irho = gt[9 * kTile], Kb = gt[10 * kTile];
   if (irho != 0.0) {
-    const double* qt = q + (size_t)tile * 4 * Np * kTile + es;
+    const T* qt = q + (size_t)tile * 4 * Np * kTile + es;
     const double rho = 1.0 / irho;
     for (int a = g; a < Np; a += 16) {
       double mq[4] = {0, 0, 0, 0};
       for (int b = 0; b < Np; ++b) {
         const double m = mass[a * Np + b];
-        for (int f = 0; f < 4; ++f) mq[f] += m * qt[(f * Np + b) * kTile];
+        for (int f = 0; f < 4; ++f) mq[f] += m * (double)qt[(f * Np + b) * kTile];
       }
-      acc += qt[a * kTile] * mq[0] / Kb +
-             rho * (qt[(Np + a) * kTile] * mq[1] + qt[(2 * Np + a) * kTile] * mq[2] +
-                    qt[(3 * Np + a) * kTile] * mq[3]);
+      acc += (double)qt[a * kTile] * mq[0] / Kb +
+             rho * ((double)qt[(Np + a) * kTile] * mq[1] + (double)qt[(2 * Np + a) * kTile] * mq[2] +
+                    (double)qt[(3 * Np + a) * kTile] * mq[3]);
     }
     acc *= 0.5 * J[e];
   }
@@ -429,9 +431,14 @@ hipError_t launch_level3(const Lvl3& L, const double* qo, double* qn, double* re
   }
 }
 
-hipError_t launch_energy(const Lvl3& L, const double* q, const double* mass, const double* J,
-                         double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_energy, dim3(L.ntile), dim3(256), 0, st, L, q, mass, J, out);
+hipError_t launch_energy(const Lvl3& L, const void* q, int q_f32, const double* mass,
+                         const double* J, double* out, hipStream_t st) {
+  if (q_f32)
+    hipLaunchKernelGGL(k_energy<float>, dim3(L.ntile), dim3(256), 0, st, L,
+                       static_cast<const float*>(q), mass, J, out);
+  else
+    hipLaunchKernelGGL(k_energy<double>, dim3(L.ntile), dim3(256), 0, st, L,
+                       static_cast<const double*>(q), mass, J, out);
   return hipGetLastError();
 }
 

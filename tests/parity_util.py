@@ -44,10 +44,11 @@ def run_oracle(case, steps, dt, t0=0.0):
     return o.s
 
 
-def make_solver(case):
+def make_solver(case, precision=0):
     from paper_1610_05023_amd import Solver
     s = Solver(case["VX"], case["E"], case["N"], case["P"], case["rho"], case["c"],
-               face_bc=case["face_bc"], periodic=case["periodic"], box=case["box"])
+               face_bc=case["face_bc"], periodic=case["periodic"], box=case["box"],
+               precision=precision)
     s.bind()
     s.set_state(case["state"])
     if case["source"] is not None:

@@ -175,3 +175,26 @@ def test_full_size_layered_one_step():
     case = make_case(n=n, N=4, P=6, medium="layered", init="random", seed=123,
                      source=((0.5 + 0.3 / n, 0.5 + 0.2 / n, 0.5 + 0.1 / n), 80.0, 0.0125))
     _check(case, 1, w.kuhn_dt(n, 4, 3.0), t0=0.01)
+
+
+@pytest.mark.parametrize("N", [4, 5])
+def test_fp32_variant_error(N):
+    """FP32 3D level (FP32 state, FP32 MFMA), FP64 boundary levels: its error
+    against the FP64 oracle (10 steps) and the FP64 library (200 steps),
+    per array, on the 8^3 x 6 mesh with HABC P = 3 on all faces and a
+    centred Gaussian that reaches the faces.  Rounding only: the bound is a
+    regression guard at a few hundred FP32 ulps, not a parity claim."""
+    n = 8
+    case = make_case(n=n, N=N, P=3, init="gaussian", width=0.15)
+    dt = w.kuhn_dt(n, N, 1.0)
+    s32 = make_solver(case, precision=2)
+    s32.step(10, dt)
+    e10 = rel_errors(s32.read_fields(), run_oracle(case, 10, dt))
+    print(f"[fp32] N={N} 10 steps vs oracle", {k: f"{v:.1e}" for k, v in e10.items()}, flush=True)
+    s32.step(190, dt, 10 * dt)
+    s64 = make_solver(case)
+    s64.step(200, dt)
+    e200 = rel_errors(s32.read_fields(), s64.read_fields())
+    print(f"[fp32] N={N} 200 steps vs FP64", {k: f"{v:.1e}" for k, v in e200.items()}, flush=True)
+    assert max(e10.values()) < 1e-4 and max(e200.values()) < 1e-3, (e10, e200)
+    assert s32.check()[0] == "DGH_OK"
