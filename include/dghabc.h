@@ -163,6 +163,54 @@ dgh_status dgh_energy(dgh_ctx* ctx, int shot, double* e);
  * dgh_set_state.  Synchronises. */
 dgh_status dgh_check(dgh_ctx* ctx, int shot, double e_ref, double rel_tol, double* e_out);
 
+/* ---- Learned boundary closure (an extension beside the method: a small
+ * MLP stands in for the order-P auxiliary recursion of Sections 2-3 on the
+ * absorbing faces).  Network: 10 inputs (p and Z |u_t| of the 3D trace at a
+ * face node, u_t the velocity tangential to the face, now and at the 4
+ * previous step ends; divided by their root mean square, times in_scale)
+ * -> 64 -> 64 -> 64 (tanh) -> y; r- = g_max tanh(y) r+ with r+ =
+ * (p + Z n.u)/2 the current outgoing characteristic, so |r-| <= |g_max|
+ * |r+| at every node and the closed loop cannot gain energy at the
+ * boundary.  A sample row is the 10 raw inputs followed by r+.  Parameters (FP32,
+ * flat, DGH_CLOSURE_PARAMS): in_scale, g_max (|g_max| <= 1), W1[64][10],
+ * b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[64], b4. */
+#define DGH_CLOSURE_PARAMS 9091
+
+/* Uses the closure for r- on every HABC face (host parameters, copied);
+ * n_w = 0 returns to the plain method.  Needs P = 0 (no auxiliary fields)
+ * and |g_max| <= 1 (DGH_EINVAL otherwise);
+ * edges and corners then have no compatibility systems.  The network runs
+ * once per step, at its end, on the traces of that step end and the 4
+ * before it (the inputs dgh_closure_sample records); its r- then holds for
+ * every stage of the next step.  dgh_set_state clears a shot's trace
+ * history and its r- (qb3). */
+dgh_status dgh_set_closure(dgh_ctx* ctx, const float* w, int n_w);
+
+/* Keeps the per-node trace history up to date at every step end (always on
+ * while a closure is set), so that dgh_closure_sample can read it. */
+dgh_status dgh_closure_record(dgh_ctx* ctx, int enable);
+
+/* Training samples of one shot from the current state: x[Ktri*Np2][11]
+ * (sample rows: the closure's raw inputs and r+) and y[Ktri*Np2] (the
+ * current qb3, i.e. the r- the method produced at the last stage).  Host
+ * arrays.
+ * Synchronises. */
+dgh_status dgh_closure_sample(dgh_ctx* ctx, int shot, float* x, float* y);
+
+/* Training kernels of the closure, no context: every pointer is a device
+ * pointer, stream a hipStream_t (NULL = default).  work: at least
+ * dgh_mlp_work_size(batch) floats.  dgh_mlp_forward: Y[n] = r- for the sample rows X[n][11].
+ * dgh_mlp_grad: G = gradient of the mean squared error (1/n) sum (r- - T)^2
+ * over the batch (G[0] = G[1] = 0); loss (host, may be NULL: then no
+ * synchronisation) receives the loss.  dgh_mlp_adam: one Adam step (beta
+ * 0.9, 0.999, eps 1e-8) at step t >= 1 on every parameter but the scales. */
+dgh_status dgh_mlp_work_size(int batch, size_t* floats);
+dgh_status dgh_mlp_forward(const float* W, const float* X, int n, float* Y, void* stream);
+dgh_status dgh_mlp_grad(const float* W, const float* X, const float* T, int n, float* G,
+                        float* work, double* loss, void* stream);
+dgh_status dgh_mlp_adam(float* W, const float* G, float* M, float* V, int t, float lr,
+                        void* stream);
+
 /* Per-kernel timing with HIP events on the bound stream: enable = 1 starts
  * recording around every 3D-level launch, 0 stops.  dgh_kernel_time returns
  * the accumulated milliseconds and launch count of level `level` (3, 2, 1,

@@ -42,6 +42,15 @@ _SIGS = {
     "dgh_step": [C.c_void_p, C.c_int, C.c_double, C.c_double],
     "dgh_energy": [C.c_void_p, C.c_int, C.POINTER(C.c_double)],
     "dgh_check": [C.c_void_p, C.c_int, C.c_double, C.c_double, C.POINTER(C.c_double)],
+    "dgh_set_closure": [C.c_void_p, C.c_void_p, C.c_int],
+    "dgh_closure_record": [C.c_void_p, C.c_int],
+    "dgh_closure_sample": [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p],
+    "dgh_mlp_work_size": [C.c_int, C.POINTER(C.c_size_t)],
+    "dgh_mlp_forward": [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p],
+    "dgh_mlp_grad": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                     C.POINTER(C.c_double), C.c_void_p],
+    "dgh_mlp_adam": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_float,
+                     C.c_void_p],
     "dgh_kernel_timing": [C.c_void_p, C.c_int],
     "dgh_kernel_time": [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
     "dgh_last_error": [C.c_void_p],
@@ -207,6 +216,27 @@ class Solver:
             raise DghError(f"dgh_check: {STATUS.get(st, st)}: {msg}")
         return STATUS[st], e.value
 
+    def set_closure(self, w=None):
+        """Learned closure parameters (DGH_CLOSURE_PARAMS floats), or None to
+        return to the plain method."""
+        if w is None:
+            self._call("dgh_set_closure", None, 0)
+            return
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._call("dgh_set_closure", _ptr(w), int(w.size))
+
+    def closure_record(self, enable=True):
+        self._call("dgh_closure_record", 1 if enable else 0)
+
+    def closure_sample(self, shot=0):
+        """(X[nodes][11], Y[nodes]) from the current state (float32): sample
+        rows (the closure's 10 raw inputs, then r+) and the method's r-."""
+        nn = self.counts["Ktri"] * self.counts["Np2"]
+        x = np.empty((nn, 11), dtype=np.float32)
+        y = np.empty(nn, dtype=np.float32)
+        self._call("dgh_closure_sample", shot, _ptr(x), _ptr(y))
+        return x, y
+
     def kernel_timing(self, enable):
         self._call("dgh_kernel_timing", 1 if enable else 0)
 
@@ -226,3 +256,50 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ---- training kernels of the closure (device tensors; no context)
+CLOSURE_PARAMS = 9091
+
+
+def _check(st, name):
+    if st != DGH_OK:
+        raise DghError(f"{name}: {STATUS.get(st, st)}")
+
+
+def _stream(t):
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def mlp_work_size(batch):
+    n = C.c_size_t()
+    _check(load().dgh_mlp_work_size(int(batch), C.byref(n)), "dgh_mlp_work_size")
+    return n.value
+
+
+def mlp_forward(W, X):
+    """r- for the sample rows X[n][11] (float32 CUDA tensors) -> Y[n]."""
+    import torch
+    Y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(load().dgh_mlp_forward(C.c_void_p(W.data_ptr()), C.c_void_p(X.data_ptr()),
+                                  int(X.shape[0]), C.c_void_p(Y.data_ptr()), _stream(X)),
+           "dgh_mlp_forward")
+    return Y
+
+
+def mlp_grad(W, X, T, G, work, with_loss=True):
+    """Gradient of the mean squared error into G; returns the loss (or None)."""
+    loss = C.c_double()
+    _check(load().dgh_mlp_grad(C.c_void_p(W.data_ptr()), C.c_void_p(X.data_ptr()),
+                               C.c_void_p(T.data_ptr()), int(X.shape[0]),
+                               C.c_void_p(G.data_ptr()), C.c_void_p(work.data_ptr()),
+                               C.byref(loss) if with_loss else None, _stream(X)),
+           "dgh_mlp_grad")
+    return loss.value if with_loss else None
+
+
+def mlp_adam(W, G, M, V, t, lr):
+    _check(load().dgh_mlp_adam(C.c_void_p(W.data_ptr()), C.c_void_p(G.data_ptr()),
+                               C.c_void_p(M.data_ptr()), C.c_void_p(V.data_ptr()), int(t),
+                               float(lr), _stream(W)), "dgh_mlp_adam")

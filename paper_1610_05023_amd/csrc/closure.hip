@@ -1,0 +1,427 @@
+// Learned boundary closure: a small MLP that maps the recent history of the
+// traces at an absorbing-face node to the incoming characteristic r- the 3D
+// flux needs there (the quantity the order-P auxiliary recursion of
+// Sections 2-3 produces), with hand-written training kernels.
+//
+// Inputs: p and Z |u_t| (u_t the velocity tangential to the face) at the
+// node now and at the 4 previous step ends, 10 values, divided by their own
+// root mean square (a linear boundary's reflection gain does not depend on
+// the amplitude) and times in_scale.  For a plane wave, p and Z |u_t| carry
+// the same factor whatever part of it the boundary reflects, so their ratio
+// (sin of the incidence angle) does not feed back on the closure's own
+// output; Z n.u is left out on purpose, as it would let the network copy
+// the interior's incoming characteristic, a map that in the continuum
+// imposes no condition at all.
+// Network (FP32): 10 -> 64 -> 64 -> 64 (tanh) -> y, and r- = g_max tanh(y)
+// r+ with r+ = (p + Z n.u)/2 the current outgoing characteristic.  The
+// network thus picks a reflection gain in (-g_max, g_max); with g_max <= 1
+// every node has |r-| <= |r+|, so the boundary never feeds energy back into
+// the domain whatever the weights (the energy flux through a face with the
+// upwind flux goes as r+^2 - r-^2).
+// Parameters, flat: in_scale, g_max, W1[64][10], b1[64], W2[64][64], b2[64],
+// W3[64][64], b3[64], W4[64], b4 (9091 floats; the first two are fixed, the
+// rest trained with Adam on the mean squared error of r-).  A sample row
+// holds the 10 raw inputs and r+ (11 floats).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "levels.hpp"
+
+namespace dgh {
+
+namespace {
+
+constexpr int kH = 64;              // hidden width
+constexpr int kIn = 10;             // inputs
+constexpr int kRow = kIn + 1;       // sample row: the raw inputs, then r+
+constexpr int oW1 = 2, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH,
+              oW3 = ob2 + kH, ob3 = oW3 + kH * kH, oW4 = ob3 + kH, ob4 = oW4 + kH;
+constexpr int kNW = ob4 + 1;        // 9091
+constexpr int kThreads = 256;
+constexpr int kHist = 10;           // history per node: (p, Z |u_t|) at 5 step ends
+static_assert(kHist == kIn, "the closure reads the whole history as its inputs");
+static_assert(kNW == kMlpParams, "parameter layout");
+
+// 1 / root mean square of the raw inputs (0 inputs stay 0)
+__device__ __forceinline__ float input_inv_rms(const float* xin) {
+  float q = 0.f;
+#pragma unroll
+  for (int k = 0; k < kIn; ++k) q += xin[k] * xin[k];
+  return 1.0f / sqrtf(q * (1.0f / kIn) + 1e-30f);
+}
+
+// forward of one sample; h receives the three hidden layers if non-null
+__device__ __forceinline__ float mlp_eval(const float* __restrict__ w, const float* xin,
+                                          float inv, float* __restrict__ hout, int hstride) {
+  float x[kIn];
+#pragma unroll
+  for (int k = 0; k < kIn; ++k) x[k] = w[0] * inv * xin[k];
+  float a[kH], b[kH];
+#pragma unroll
+  for (int i = 0; i < kH; ++i) {
+    float s = w[ob1 + i];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) s += w[oW1 + i * kIn + k] * x[k];
+    a[i] = tanhf(s);
+    if (hout) hout[i * hstride] = a[i];
+  }
+#pragma unroll
+  for (int i = 0; i < kH; ++i) {
+    float s = w[ob2 + i];
+#pragma unroll
+    for (int k = 0; k < kH; ++k) s += w[oW2 + i * kH + k] * a[k];
+    b[i] = tanhf(s);
+    if (hout) hout[(kH + i) * hstride] = b[i];
+  }
+#pragma unroll
+  for (int i = 0; i < kH; ++i) {
+    float s = w[ob3 + i];
+#pragma unroll
+    for (int k = 0; k < kH; ++k) s += w[oW3 + i * kH + k] * b[k];
+    a[i] = tanhf(s);
+    if (hout) hout[(2 * kH + i) * hstride] = a[i];
+  }
+  float y = w[ob4];
+#pragma unroll
+  for (int k = 0; k < kH; ++k) y += w[oW4 + k] * a[k];
+  return y;
+}
+
+// Forward over n sample rows X[n][11]: Y[n] = r-; H (if non-null) gets the
+// hidden layers column-major, H[l][s] for l < 192, Th[s] = tanh(y) and
+// Inv[s] = 1 / rms of the raw inputs.
+__global__ void __launch_bounds__(kThreads) k_mlp_fwd(const float* __restrict__ W,
+                                                      const float* __restrict__ X, int n,
+                                                      float* __restrict__ H,
+                                                      float* __restrict__ Th,
+                                                      float* __restrict__ Inv,
+                                                      float* __restrict__ Y) {
+  __shared__ float w[kNW];
+  for (int i = threadIdx.x; i < kNW; i += blockDim.x) w[i] = W[i];
+  __syncthreads();
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  float x[kIn];
+#pragma unroll
+  for (int k = 0; k < kIn; ++k) x[k] = X[(size_t)s * kRow + k];
+  const float inv = input_inv_rms(x);
+  const float th = tanhf(mlp_eval(w, x, inv, H ? H + s : nullptr, n));
+  if (H) {
+    Th[s] = th;
+    Inv[s] = inv;
+  }
+  Y[s] = w[1] * th * X[(size_t)s * kRow + kIn];
+}
+
+// Backward through the activations of one batch: with the loss
+// L = (1/n) sum_s (Y_s - T_s)^2, dY = dL/dy (y the output layer's value)
+// and dH[l][s] = dL/d(pre-activation of hidden unit l).  lossp[block] gets
+// the block's partial sum of squared errors.
+__global__ void __launch_bounds__(kThreads) k_mlp_bwd(const float* __restrict__ W,
+                                                      const float* __restrict__ X,
+                                                      const float* __restrict__ T, int n,
+                                                      const float* __restrict__ H,
+                                                      const float* __restrict__ Th,
+                                                      const float* __restrict__ Y,
+                                                      float* __restrict__ dY,
+                                                      float* __restrict__ dH,
+                                                      float* __restrict__ lossp) {
+  __shared__ float w[kNW];
+  __shared__ float red[kThreads];
+  for (int i = threadIdx.x; i < kNW; i += blockDim.x) w[i] = W[i];
+  __syncthreads();
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  float sq = 0.f;
+  if (s < n) {
+    const float e = Y[s] - T[s];
+    sq = e * e;
+    const float th = Th[s];
+    const float rp = X[(size_t)s * kRow + kIn];
+    const float dy = 2.f * e / (float)n * w[1] * rp * (1.f - th * th);
+    dY[s] = dy;
+    float g3[kH], g2[kH];
+#pragma unroll
+    for (int j = 0; j < kH; ++j) {
+      const float h = H[(size_t)(2 * kH + j) * n + s];
+      g3[j] = w[oW4 + j] * dy * (1.f - h * h);
+      dH[(size_t)(2 * kH + j) * n + s] = g3[j];
+    }
+#pragma unroll
+    for (int i = 0; i < kH; ++i) {
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < kH; ++j) acc += w[oW3 + j * kH + i] * g3[j];
+      const float h = H[(size_t)(kH + i) * n + s];
+      g2[i] = acc * (1.f - h * h);
+      dH[(size_t)(kH + i) * n + s] = g2[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kH; ++i) {
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < kH; ++j) acc += w[oW2 + j * kH + i] * g2[j];
+      const float h = H[(size_t)i * n + s];
+      dH[(size_t)i * n + s] = acc * (1.f - h * h);
+    }
+  }
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  for (int k = kThreads / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) lossp[blockIdx.x] = red[0];
+}
+
+// Parameter gradients: one thread per parameter, summed over the batch
+// (dW = dH^T * previous layer, db = sum dH).  G[0], G[1] (scales) = 0.
+__global__ void __launch_bounds__(kThreads) k_mlp_wgrad(const float* __restrict__ W,
+                                                        const float* __restrict__ X, int n,
+                                                        const float* __restrict__ H,
+                                                        const float* __restrict__ Inv,
+                                                        const float* __restrict__ dY,
+                                                        const float* __restrict__ dH,
+                                                        float* __restrict__ G) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kNW) return;
+  const float sin_ = W[0];
+  float acc = 0.f;
+  if (p < oW1) {
+    acc = 0.f;
+  } else if (p < ob1) {                       // W1[i][k]: dH1[i] x[k] in_scale / rms
+    const int i = (p - oW1) / kIn, k = (p - oW1) % kIn;
+    for (int s = 0; s < n; ++s)
+      acc += dH[(size_t)i * n + s] * (X[(size_t)s * kRow + k] * Inv[s]);
+    acc *= sin_;
+  } else if (p < oW2) {                       // b1
+    const int i = p - ob1;
+    for (int s = 0; s < n; ++s) acc += dH[(size_t)i * n + s];
+  } else if (p < ob2) {                       // W2[i][k]: dH2[i] h1[k]
+    const int i = (p - oW2) / kH, k = (p - oW2) % kH;
+    for (int s = 0; s < n; ++s) acc += dH[(size_t)(kH + i) * n + s] * H[(size_t)k * n + s];
+  } else if (p < oW3) {                       // b2
+    const int i = p - ob2;
+    for (int s = 0; s < n; ++s) acc += dH[(size_t)(kH + i) * n + s];
+  } else if (p < ob3) {                       // W3[i][k]: dH3[i] h2[k]
+    const int i = (p - oW3) / kH, k = (p - oW3) % kH;
+    for (int s = 0; s < n; ++s)
+      acc += dH[(size_t)(2 * kH + i) * n + s] * H[(size_t)(kH + k) * n + s];
+  } else if (p < oW4) {                       // b3
+    const int i = p - ob3;
+    for (int s = 0; s < n; ++s) acc += dH[(size_t)(2 * kH + i) * n + s];
+  } else if (p < ob4) {                       // W4[k]: dY h3[k]
+    const int k = p - oW4;
+    for (int s = 0; s < n; ++s) acc += dY[s] * H[(size_t)(2 * kH + k) * n + s];
+  } else {                                    // b4
+    for (int s = 0; s < n; ++s) acc += dY[s];
+  }
+  G[p] = acc;
+}
+
+// Adam (Kingma & Ba) on the trained parameters (index >= 2), step t >= 1.
+__global__ void k_adam(float* __restrict__ W, const float* __restrict__ G, float* __restrict__ M,
+                       float* __restrict__ V, int t, float lr, float b1, float b2, float eps) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < oW1 || p >= kNW) return;
+  const float g = G[p];
+  const float m = b1 * M[p] + (1.f - b1) * g;
+  const float v = b2 * V[p] + (1.f - b2) * g * g;
+  M[p] = m;
+  V[p] = v;
+  const float mh = m / (1.f - powf(b1, (float)t)), vh = v / (1.f - powf(b2, (float)t));
+  W[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// Traces of the new 3D state at triangle node (t, a): p, Z n.u and Z |u_t|
+// (the face normal is the axis ax with sign sgn).
+template <class T3>
+__device__ __forceinline__ void node_trace(const Lvl2& L2, const T3* __restrict__ q3, int np3,
+                                           int t, int a, float& p, float& zun, float& zut) {
+  const int* inf = L2.info + (size_t)t * 8;
+  const int e3 = inf[0], ax = inf[1], sgn = inf[2];
+  const int n3 = L2.tetnode[(size_t)t * L2.Np + a];
+  const T3* q = q3 + (size_t)(e3 >> 4) * 4 * np3 * kTile + (e3 & 15);
+  const double Z = L2.geo[(size_t)t * 8 + 6];
+  const double un = (double)q[((1 + ax) * np3 + n3) * kTile];
+  const double ua = (double)q[((1 + (ax + 1) % 3) * np3 + n3) * kTile];
+  const double ub = (double)q[((1 + (ax + 2) % 3) * np3 + n3) * kTile];
+  p = (float)q[n3 * kTile];
+  zun = (float)(Z * (double)sgn * un);
+  zut = (float)(Z * sqrt(ua * ua + ub * ub));
+}
+
+// End of a step with the closure on: the history moves one step back and
+// takes the current traces first (as k_hist_push), then r- at every
+// absorbing-face node comes from the current traces and the 4 step ends
+// before them -> qb3, which every stage of the next step reads; q0_3 =
+// r+ + r- (kept for symmetry with the face rule).  The inputs are those
+// k_closure_sample records after a step of the plain method.  One thread
+// per node.
+template <class T3>
+__global__ void __launch_bounds__(kThreads) k_closure(Lvl2 L2, const float* __restrict__ W,
+                                                      const T3* __restrict__ q3, int np3,
+                                                      float* __restrict__ hist,
+                                                      double* __restrict__ qb3,
+                                                      double* __restrict__ q03, Shots sh) {
+  __shared__ float w[kNW];
+  for (int i = threadIdx.x; i < kNW; i += blockDim.x) w[i] = W[i];
+  __syncthreads();
+  const size_t k = blockIdx.y;
+  q3 += k * sh.st3;
+  qb3 += k * sh.stb3;
+  q03 += k * sh.stb3;
+  const int nn = L2.Kt * L2.Np;
+  hist += k * (size_t)nn * kHist;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nn) return;
+  const int t = x / L2.Np, a = x - t * L2.Np;
+  float f[kHist], zun;
+  node_trace(L2, q3, np3, t, a, f[0], zun, f[1]);
+#pragma unroll
+  for (int j = 0; j < kHist - 2; ++j) f[2 + j] = hist[(size_t)x * kHist + j];
+  float* o = hist + (size_t)x * kHist;
+#pragma unroll
+  for (int j = 0; j < kHist; ++j) o[j] = f[j];
+  const float rpf = 0.5f * (f[0] + zun);
+  const float th = tanhf(mlp_eval(w, f, input_inv_rms(f), nullptr, 0));
+  const double rm = (double)(w[1] * th * rpf);
+  qb3[x] = rm;
+  q03[x] = (double)rpf + rm;
+}
+
+// End of a step: the history (5 step ends, most recent first) moves one
+// step back and takes the current traces as its most recent entry.
+template <class T3>
+__global__ void __launch_bounds__(kThreads) k_hist_push(Lvl2 L2, const T3* __restrict__ q3,
+                                                        int np3, float* __restrict__ hist,
+                                                        Shots sh) {
+  const size_t k = blockIdx.y;
+  q3 += k * sh.st3;
+  const int nn = L2.Kt * L2.Np;
+  hist += k * (size_t)nn * kHist;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nn) return;
+  const int t = x / L2.Np, a = x - t * L2.Np;
+  float p, zun, zut;
+  node_trace(L2, q3, np3, t, a, p, zun, zut);
+  float h[kHist];
+#pragma unroll
+  for (int j = 0; j < kHist; ++j) h[j] = hist[(size_t)x * kHist + j];
+  float* o = hist + (size_t)x * kHist;
+  o[0] = p;
+  o[1] = zut;
+#pragma unroll
+  for (int j = 2; j < kHist; ++j) o[j] = h[j - 2];
+}
+
+// Training samples of one shot, taken after a step end (whose traces the
+// history already holds first): X[node][11] = the raw inputs (the current
+// p, Z |u_t| and the 4 step ends before them) and r+, Y[node] = the current
+// qb3 -- the r- the face rule produced at the step's last stage.
+template <class T3>
+__global__ void __launch_bounds__(kThreads) k_closure_sample(Lvl2 L2, const T3* __restrict__ q3,
+                                                             int np3, const float* __restrict__ hist,
+                                                             const double* __restrict__ qb3,
+                                                             float* __restrict__ X,
+                                                             float* __restrict__ Y) {
+  const int nn = L2.Kt * L2.Np;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nn) return;
+  const int t = x / L2.Np, a = x - t * L2.Np;
+  float p, zun, zut;
+  node_trace(L2, q3, np3, t, a, p, zun, zut);
+  float* r = X + (size_t)x * kRow;
+  r[0] = p;
+  r[1] = zut;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) r[2 + j] = hist[(size_t)x * kHist + 2 + j];
+  r[kIn] = 0.5f * (p + zun);
+  Y[x] = (float)qb3[x];
+}
+
+}  // namespace
+
+// work: H[192][n], dH[192][n], Y[n], dY[n], Th[n], Inv[n], then the loss partials
+size_t mlp_work_floats(int n) { return (size_t)n * (2 * 3 * kH + 4) + (n + kThreads - 1) / kThreads; }
+
+hipError_t mlp_forward(const float* W, const float* X, int n, float* Y, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mlp_fwd, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, st, W, X,
+                     n, nullptr, nullptr, nullptr, Y);
+  return hipGetLastError();
+}
+
+hipError_t mlp_grad(const float* W, const float* X, const float* T, int n, float* G, float* work,
+                    hipStream_t st) {
+  if (n <= 0) return hipErrorInvalidValue;
+  float* H = work;
+  float* dH = H + (size_t)n * 3 * kH;
+  float* Y = dH + (size_t)n * 3 * kH;
+  float* dY = Y + n;
+  float* Th = dY + n;
+  float* Inv = Th + n;
+  float* lossp = Inv + n;
+  const dim3 gs((n + kThreads - 1) / kThreads), bs(kThreads);
+  hipLaunchKernelGGL(k_mlp_fwd, gs, bs, 0, st, W, X, n, H, Th, Inv, Y);
+  hipLaunchKernelGGL(k_mlp_bwd, gs, bs, 0, st, W, X, T, n, H, Th, Y, dY, dH, lossp);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3((kNW + kThreads - 1) / kThreads), bs, 0, st, W, X, n, H, Inv,
+                     dY, dH, G);
+  return hipGetLastError();
+}
+
+hipError_t mlp_adam(float* W, const float* G, float* M, float* V, int t, float lr, float b1,
+                    float b2, float eps, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3((kNW + kThreads - 1) / kThreads), dim3(kThreads), 0, st, W, G, M,
+                     V, t, lr, b1, b2, eps);
+  return hipGetLastError();
+}
+
+const float* mlp_loss_partials(const float* work, int n) {
+  return work + (size_t)n * (2 * 3 * kH + 4);
+}
+
+hipError_t launch_closure(const Lvl2& L2, const float* W, const void* q3, int q3f32, int np3,
+                          float* hist, double* qb3, double* q03, const Shots& sh,
+                          hipStream_t st) {
+  const int nn = L2.Kt * L2.Np;
+  if (nn == 0) return hipSuccess;
+  const dim3 g((nn + kThreads - 1) / kThreads, sh.n), b(kThreads);
+  if (q3f32)
+    hipLaunchKernelGGL(k_closure<float>, g, b, 0, st, L2, W, static_cast<const float*>(q3), np3,
+                       hist, qb3, q03, sh);
+  else
+    hipLaunchKernelGGL(k_closure<double>, g, b, 0, st, L2, W, static_cast<const double*>(q3), np3,
+                       hist, qb3, q03, sh);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_push(const Lvl2& L2, const void* q3, int q3f32, int np3, float* hist,
+                            const Shots& sh, hipStream_t st) {
+  const int nn = L2.Kt * L2.Np;
+  if (nn == 0) return hipSuccess;
+  const dim3 g((nn + kThreads - 1) / kThreads, sh.n), b(kThreads);
+  if (q3f32)
+    hipLaunchKernelGGL(k_hist_push<float>, g, b, 0, st, L2, static_cast<const float*>(q3), np3,
+                       hist, sh);
+  else
+    hipLaunchKernelGGL(k_hist_push<double>, g, b, 0, st, L2, static_cast<const double*>(q3), np3,
+                       hist, sh);
+  return hipGetLastError();
+}
+
+hipError_t launch_closure_sample(const Lvl2& L2, const void* q3, int q3f32, int np3,
+                                 const float* hist, const double* qb3, float* X, float* Y,
+                                 hipStream_t st) {
+  const int nn = L2.Kt * L2.Np;
+  if (nn == 0) return hipSuccess;
+  const dim3 g((nn + kThreads - 1) / kThreads), b(kThreads);
+  if (q3f32)
+    hipLaunchKernelGGL(k_closure_sample<float>, g, b, 0, st, L2, static_cast<const float*>(q3),
+                       np3, hist, qb3, X, Y);
+  else
+    hipLaunchKernelGGL(k_closure_sample<double>, g, b, 0, st, L2, static_cast<const double*>(q3),
+                       np3, hist, qb3, X, Y);
+  return hipGetLastError();
+}
+
+}  // namespace dgh

@@ -38,6 +38,7 @@ struct Layout {
   Region q2[2], res2, qb3, q03, geo2, info2, tetnode2, nbrnode2, ops2, fmask2, gamma;
   Region q1[2], res1, qb2, q02, geo1, info1, trinode1, ops1, cji, cij, G, H;
   Region qb1, info0, nrm0, T, srcw, srcp, wlines, wcorners, flags, ops2f;
+  Region mlpw, hist, csamp;   // learned closure: parameters, trace history, samples
   // per-shot strides (doubles) of the state arrays
   size_t st3 = 0, st2 = 0, stb3 = 0, st1 = 0, stb2 = 0, stb1 = 0;
   size_t e3 = 8;   // bytes per element of the 3D state (8 FP64, 4 FP32)
@@ -81,6 +82,8 @@ struct dgh_ctx {
   dgh::Lvl0 L0{};
   dgh::LvlB LB{};
   std::vector<int> wlines, wcorners;  // line-group work list (host copy)
+  bool closure = false;               // learned closure replaces the face level
+  bool record = false;                // keep the trace history for sampling
   dgh::LvlF LF{};
 };
 
@@ -470,6 +473,10 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.wcorners, std::max<size_t>(1, c->wcorners.size()) * i4);
   L.add(L.flags, (size_t)dgh::kScanMax * dgh::kScanBlocks * i4);
   L.add(L.ops2f, (size_t)dgh::frag2_size(m.N) * d);
+  const size_t nnode = (size_t)std::max(1, Kt * Np2);
+  L.add(L.mlpw, (size_t)dgh::kMlpParams * sizeof(float));
+  L.add(L.hist, S * nnode * 10 * sizeof(float));
+  L.add(L.csamp, nnode * 12 * sizeof(float));   // rows of 11, then targets
 }
 
 template <class V>
@@ -799,6 +806,11 @@ dgh_status dgh_set_state(dgh_ctx* c, int shot, const double* const* arr) {
       HIPCHECK(c, hipMemset(dst, 0, it.n * sizeof(double)));
     }
   }
+  // a new state has no past: the closure's trace history starts at zero
+  const size_t nn = (size_t)m.Ktri * m.tri.Np;
+  if (nn > 0)
+    HIPCHECK(c, hipMemset(c->ws + L.hist.off + shot * nn * 10 * sizeof(float), 0,
+                          nn * 10 * sizeof(float)));
   HIPCHECK(c, hipDeviceSynchronize());
   return DGH_OK;
 }
@@ -927,7 +939,7 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
         HIPCHECK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
       }
-      {
+      if (!c->closure) {   // with the closure, qb3 holds from the last step end
         const dgh::FaceBufs fb{dptr<double>(c, L.q2[o]), dptr<double>(c, L.q2[n]),
                                dptr<double>(c, L.res2), dptr<double>(c, L.qb3),
                                dptr<double>(c, L.q03), c->ws + L.q3[n].off,
@@ -943,6 +955,14 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
                                        dptr<double>(c, L.q02), kA[s], kB[s], dt, sh, c->stream));
       c->cur = n;
     }
+    if (c->closure)
+      HIPCHECK(c, dgh::launch_closure(c->L2, dptr<float>(c, L.mlpw), c->ws + L.q3[c->cur].off,
+                                      L.e3 == 4 ? 1 : 0, c->mesh.tet.Np, dptr<float>(c, L.hist),
+                                      dptr<double>(c, L.qb3), dptr<double>(c, L.q03), sh,
+                                      c->stream));
+    else if (c->record)
+      HIPCHECK(c, dgh::launch_hist_push(c->L2, c->ws + L.q3[c->cur].off, L.e3 == 4 ? 1 : 0,
+                                        c->mesh.tet.Np, dptr<float>(c, L.hist), sh, c->stream));
   }
   return DGH_OK;
 }
@@ -1009,6 +1029,92 @@ dgh_status dgh_check(dgh_ctx* c, int shot, double e_ref, double rel_tol, double*
   if (e_ref > 0.0 && e > e_ref * (1.0 + rel_tol))
     return fail(c, DGH_EUNSTABLE, "energy grew beyond the reference");
   return DGH_OK;
+}
+
+dgh_status dgh_set_closure(dgh_ctx* c, const float* w, int n_w) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "set_closure before bind");
+  if (n_w == 0) {
+    c->closure = false;
+    return DGH_OK;
+  }
+  if (!w || n_w != dgh::kMlpParams) return fail(c, DGH_EINVAL, "closure needs DGH_CLOSURE_PARAMS floats");
+  if (c->P != 0) return fail(c, DGH_EINVAL, "the closure replaces the auxiliary fields: set P = 0");
+  for (int i = 0; i < n_w; ++i)
+    if (!std::isfinite(w[i])) return fail(c, DGH_EINVAL, "closure parameters must be finite");
+  if (!(std::fabs(w[1]) <= 1.0f))
+    return fail(c, DGH_EINVAL, "closure gain bound |g_max| must not exceed 1");
+  HIPCHECK(c, hipMemcpy(c->ws + c->lay.mlpw.off, w, (size_t)n_w * sizeof(float),
+                        hipMemcpyHostToDevice));
+  c->closure = true;
+  return DGH_OK;
+}
+
+dgh_status dgh_closure_record(dgh_ctx* c, int enable) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "closure_record before bind");
+  c->record = enable != 0;
+  return DGH_OK;
+}
+
+dgh_status dgh_closure_sample(dgh_ctx* c, int shot, float* x, float* y) {
+  if (!c || !x || !y) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "closure_sample before bind");
+  if (shot < 0 || shot >= c->n_shots) return fail(c, DGH_EINVAL, "shot out of range");
+  const Layout& L = c->lay;
+  const dgh::Mesh& m = c->mesh;
+  const size_t nn = (size_t)m.Ktri * m.tri.Np;
+  if (nn == 0) return DGH_OK;
+  float* X = dptr<float>(c, L.csamp);
+  float* Y = X + nn * 11;
+  HIPCHECK(c, dgh::launch_closure_sample(
+                  c->L2, c->ws + L.q3[c->cur].off + shot * L.st3 * L.e3, L.e3 == 4 ? 1 : 0,
+                  m.tet.Np, dptr<float>(c, L.hist) + shot * nn * 10,
+                  dptr<double>(c, L.qb3) + shot * L.stb3, X, Y, c->stream));
+  HIPCHECK(c, hipMemcpyAsync(x, X, nn * 11 * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHECK(c, hipMemcpyAsync(y, Y, nn * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  return DGH_OK;
+}
+
+dgh_status dgh_mlp_work_size(int batch, size_t* floats) {
+  if (batch <= 0 || !floats) return DGH_EINVAL;
+  *floats = dgh::mlp_work_floats(batch);
+  return DGH_OK;
+}
+
+dgh_status dgh_mlp_forward(const float* W, const float* X, int n, float* Y, void* stream) {
+  if (!W || (n > 0 && (!X || !Y)) || n < 0) return DGH_EINVAL;
+  return dgh::mlp_forward(W, X, n, Y, static_cast<hipStream_t>(stream)) == hipSuccess ? DGH_OK
+                                                                                    : DGH_EHIP;
+}
+
+dgh_status dgh_mlp_grad(const float* W, const float* X, const float* T, int n, float* G,
+                        float* work, double* loss, void* stream) {
+  if (!W || !X || !T || !G || !work || n <= 0) return DGH_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dgh::mlp_grad(W, X, T, n, G, work, st) != hipSuccess) return DGH_EHIP;
+  if (loss) {
+    const int nb = (n + 255) / 256;
+    std::vector<float> part(nb);
+    if (hipMemcpyAsync(part.data(), dgh::mlp_loss_partials(work, n), nb * sizeof(float),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return DGH_EHIP;
+    double sum = 0.0;
+    for (float v : part) sum += v;
+    *loss = sum / n;
+  }
+  return DGH_OK;
+}
+
+dgh_status dgh_mlp_adam(float* W, const float* G, float* M, float* V, int t, float lr,
+                        void* stream) {
+  if (!W || !G || !M || !V || t < 1 || !(lr > 0)) return DGH_EINVAL;
+  return dgh::mlp_adam(W, G, M, V, t, lr, 0.9f, 0.999f, 1e-8f, static_cast<hipStream_t>(stream)) ==
+                 hipSuccess
+             ? DGH_OK
+             : DGH_EHIP;
 }
 
 dgh_status dgh_kernel_timing(dgh_ctx* c, int enable) {

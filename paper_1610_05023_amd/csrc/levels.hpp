@@ -156,6 +156,24 @@ inline int frag2_size(int N) {
   return (2 * RG * RG + RG * 3 * EK) * 16;
 }
 
+// Learned closure (closure.hip): MLP parameters, flat, FP32.
+constexpr int kMlpParams = 9091;
+size_t mlp_work_floats(int n);
+const float* mlp_loss_partials(const float* work, int n);
+hipError_t mlp_forward(const float* W, const float* X, int n, float* Y, hipStream_t st);
+hipError_t mlp_grad(const float* W, const float* X, const float* T, int n, float* G, float* work,
+                    hipStream_t st);
+hipError_t mlp_adam(float* W, const float* G, float* M, float* V, int t, float lr, float b1,
+                    float b2, float eps, hipStream_t st);
+hipError_t launch_closure(const Lvl2& L2, const float* W, const void* q3, int q3f32, int np3,
+                          float* hist, double* qb3, double* q03, const Shots& sh,
+                          hipStream_t st);
+hipError_t launch_hist_push(const Lvl2& L2, const void* q3, int q3f32, int np3, float* hist,
+                            const Shots& sh, hipStream_t st);
+hipError_t launch_closure_sample(const Lvl2& L2, const void* q3, int q3f32, int np3,
+                                 const float* hist, const double* qb3, float* X, float* Y,
+                                 hipStream_t st);
+
 // Arrays scanned by the finiteness check (at most kScanMax of them); the
 // kernel writes one int per (array, block): 1 if a non-finite value was seen.
 constexpr int kScanMax = 12;

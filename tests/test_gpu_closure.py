@@ -1,0 +1,137 @@
+"""The learned boundary closure on the GPU: its forward and gradient kernels
+against the FP64 reference network, its place in the step, and what a
+trained network gains over the method without auxiliary fields (the basic
+ABC), judged against a run on a domain twice as large."""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle.closure import NPARAM, forward, init_params, loss_and_grad
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def test_mlp_kernels_match_reference():
+    import torch
+    from paper_1610_05023_amd import binding as B
+    rng = np.random.default_rng(11)
+    wts = init_params(4, in_scale=2.0, g_max=0.3)
+    wts[2:] += 0.02 * rng.standard_normal(NPARAM - 2)
+    X = (0.4 * rng.standard_normal((3000, 11))).astype(np.float32)
+    T = (0.2 * rng.standard_normal(3000)).astype(np.float32)
+    dev = torch.device("cuda", 0)
+    Wd = torch.from_numpy(wts.astype(np.float32)).to(dev)
+    Xd, Td = torch.from_numpy(X).to(dev), torch.from_numpy(T).to(dev)
+    y = B.mlp_forward(Wd, Xd).cpu().numpy()
+    yr, _ = forward(wts.astype(np.float32).astype(np.float64), X.astype(np.float64))
+    G = torch.zeros_like(Wd)
+    work = torch.empty(B.mlp_work_size(3000), dtype=torch.float32, device=dev)
+    loss = B.mlp_grad(Wd, Xd, Td, G, work)
+    lr_, gr = loss_and_grad(wts.astype(np.float32).astype(np.float64), X.astype(np.float64),
+                            T.astype(np.float64))
+    ef, eg = _rel(y, yr), _rel(G.cpu().numpy(), gr)
+    print(f"[mlp] forward rel {ef:.1e}, loss {loss:.6e} vs {lr_:.6e}, gradient rel {eg:.1e}",
+          flush=True)
+    assert ef < 2e-6 and abs(loss - lr_) < 1e-5 * lr_ and eg < 1e-4
+    # one Adam step moves every trained parameter against its gradient
+    M, V = torch.zeros_like(Wd), torch.zeros_like(Wd)
+    W0 = Wd.clone()
+    B.mlp_adam(Wd, G, M, V, 1, 1e-3)
+    step = (Wd - W0).cpu().numpy()
+    g = G.cpu().numpy()
+    assert np.all(step[:2] == 0.0)
+    big = np.abs(g[2:]) > 1e-6
+    assert np.all(np.sign(step[2:][big]) == -np.sign(g[2:][big]))
+
+
+def test_zero_network_is_the_basic_abc():
+    """A closure that returns r- = 0 everywhere reproduces the method with
+    P = 0 (the basic ABC) bit for bit."""
+    from paper_1610_05023_amd import Solver
+    n, N = 4, 3
+    VX, E = w.kuhn_mesh(n)
+    K = E.shape[0]
+    q3 = w.random_array((K, 4, (N + 1) * (N + 2) * (N + 3) // 6), 5)
+    out = []
+    for use in (False, True):
+        s = Solver(VX, E, N, 0, np.ones(K), np.ones(K)).bind()
+        s.set_state({"q3": q3})
+        if use:
+            wts = np.zeros(NPARAM, dtype=np.float32)
+            wts[0] = wts[1] = 1.0
+            s.set_closure(wts)
+        s.step(20, 1e-3)
+        out.append(s.read_fields(["q3", "qb3"]))
+    assert np.array_equal(out[0]["q3"], out[1]["q3"])
+    assert np.array_equal(out[0]["qb3"], out[1]["qb3"])
+    # a gain bound above 1 could feed energy back in: refused
+    from paper_1610_05023_amd.binding import DghError
+    s = Solver(VX, E, N, 0, np.ones(K), np.ones(K)).bind()
+    bad = np.zeros(NPARAM, dtype=np.float32)
+    bad[0], bad[1] = 1.0, 1.5
+    with pytest.raises(DghError):
+        s.set_closure(bad)
+
+
+def _reflection_error(closure=None, P=0, center=(0.42, 0.55, 0.61), steps=650):
+    """q3 on the unit cube after `steps` steps vs the run on [-0.5, 1.5]^3
+    (same cells; nothing reflected there reaches the unit cube in time)."""
+    from paper_1610_05023_amd import Solver
+    from paper_1610_05023_amd.closure import gaussian_state
+    n, N, width = 8, 3, 0.15
+    dt = w.kuhn_dt(n, N, 1.0)
+
+    def run(big, P, closure):
+        VX, E = w.kuhn_mesh(2 * n, lo=(-0.5,) * 3, hi=(1.5,) * 3) if big else w.kuhn_mesh(n)
+        K = E.shape[0]
+        s = Solver(VX, E, N, P, np.ones(K), np.ones(K)).bind()
+        s.set_state(gaussian_state(s, center, width))
+        if closure is not None:
+            s.set_closure(closure)
+        s.step(steps, dt)
+        return s.read_fields(["q3"])["q3"]
+
+    i, j, k = w.cell_index_of_element(n)
+    t = np.arange(6 * n ** 3) % 6
+    idx = (((k + n // 2) * 2 * n + (j + n // 2)) * 2 * n + (i + n // 2)) * 6 + t
+    ref = run(True, 0, None)[idx]
+    return _rel(run(False, P, closure), ref)
+
+
+def test_trained_closure_beats_basic_abc():
+    from paper_1610_05023_amd.closure import teacher_samples, train
+    n, N = 8, 3
+    VX, E = w.kuhn_mesh(n)
+    K = E.shape[0]
+    centers = np.random.default_rng(5).uniform(0.3, 0.7, size=(6, 3))
+    X, Y = teacher_samples(VX, E, N, 6, np.ones(K), np.ones(K), w.kuhn_dt(n, N, 1.0), centers,
+                           0.15, steps=700, every=10, start=60)
+    wts, losses = train(X, Y, iters=2500, batch=4096, lr=1e-3, seed=5, log_every=500)
+    print(f"[closure] {len(Y)} samples, losses {[(t, f'{l:.3e}') for t, l in losses]}",
+          f"target mean square {float(np.mean(Y.astype(np.float64) ** 2)):.3e}", flush=True)
+    e0 = _reflection_error(P=0)
+    e6 = _reflection_error(P=6)
+    em = _reflection_error(closure=wts)
+    print(f"[closure] held-out pulse, error vs 2x domain: basic ABC {e0:.3e}, "
+          f"closure {em:.3e}, HABC P=6 {e6:.3e}", flush=True)
+    assert em < e0
+    # the bounded gain keeps the closed loop dissipative on a long run
+    from paper_1610_05023_amd import Solver
+    from paper_1610_05023_amd.closure import gaussian_state
+    s = Solver(VX, E, N, 0, np.ones(K), np.ones(K)).bind()
+    s.set_state(gaussian_state(s, (0.3, 0.62, 0.5), 0.15))
+    s.set_closure(wts)
+    e_start = s.energy()
+    energies = []
+    for _ in range(6):
+        s.step(500, w.kuhn_dt(n, N, 1.0))
+        st, e = s.check(e_ref=e_start, rel_tol=1e-9)
+        assert st == "DGH_OK", st
+        energies.append(e)
+    print(f"[closure] energy over 3000 steps: {e_start:.3e} -> "
+          f"{', '.join(f'{e:.2e}' for e in energies)}", flush=True)
+    assert all(b <= a * (1 + 1e-9) for a, b in zip([e_start] + energies, energies))
