@@ -249,7 +249,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
-                     "kernel": "k_level3 (3D volume + surface + LSRK update)",
+                     "kernel": ("k_level3_dma" if wl["N"] <= 4 and prec == 0 else
+                                "k_level3_f32" if prec != 0 else "k_level3") +
+                               " (3D volume + surface + LSRK update)",
                      "avg_us": avg3_ms * 1e3, "alg_bytes_per_launch": alg},
         "cpu_baseline": cpu,
     }

@@ -344,6 +344,345 @@ __device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restric
   }
 }
 
+// ---------------------------------------------- 3D, tile held on chip ---
+// The same stage for N <= 4 with one wave per SIMD (one workgroup of four
+// waves per CU).  Each wave owns an LDS buffer that receives its next tile
+// (state, geometry, impedances, face codes) by direct buffer-to-LDS loads,
+// issued once the surface term has read the current tile's copy and before
+// the update's stores, so the tile lands while the wave finishes the current
+// one.  The wave holds the tile's q in registers (the B-fragment rows a lane
+// holds for the volume term, nodes 4 j + g of element l%16, are the
+// D-fragment rows it updates), reads the own traces from the LDS copy, and
+// has the exterior traces of faces 0-2 in flight during the volume term (face
+// 3's during face 0), so each value of q and res crosses HBM once; the
+// neighbour traces are re-read, mostly from L2.
+constexpr int kWavesR = 4;
+
+template <int N>
+struct BufR {
+  static constexpr int Np = Dims3<N>::Np;
+  static constexpr int QK = (Np + 1) / 2;           // 1 KB loads for the state (512 Np bytes)
+  static constexpr int QB = QK * 1024;              // geometry, impedances, codes after it
+  static constexpr int GEO = QB, ZN = QB + 2048, NBR = QB + 3072;
+  static constexpr int BYTES = QB + 4096;
+};
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// direct loads of work item `item` (this wave's tile, shot) into buf; a tile
+// past the end loads the last tile (never used).  Each instruction moves
+// 16 bytes per lane to buf + 16 lane.
+template <int N>
+__device__ __forceinline__ void tile_dma(const Lvl3& L, const double* __restrict__ qo,
+                                         const Shots& sh, long long item, int ngrp, char* buf,
+                                         int lane) {
+  using D = Dims3<N>;
+  using BR = BufR<N>;
+  constexpr unsigned TS = 4 * D::Np * kTile * 8;
+  const int shot = (int)(item / ngrp);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tile = min((int)(item - (long long)shot * ngrp) * kWavesR + wv, L.ntile - 1);
+  const Rsrc Rq = rsrc(qo + shot * sh.st3, (unsigned)L.ntile * TS);
+  const Rsrc Rg = rsrc(L.geo, (unsigned)L.ntile * 12 * kTile * 8);
+  const Rsrc Rz = rsrc(L.zn, (unsigned)L.ntile * 4 * kTile * 8);
+  const Rsrc Rc = rsrc(L.nbr, (unsigned)L.ntile * 4 * kTile * 4);
+  const int vo = lane * 16;
+#pragma unroll
+  for (int k = 0; k < BR::QK; ++k)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(Rq, (lds_ptr)(buf + k * 1024), 16, vo,
+                                             (int)((unsigned)tile * TS + k * 1024), 0, 0);
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(Rg, (lds_ptr)(buf + BR::GEO + k * 1024), 16, vo,
+                                             tile * 12 * kTile * 8 + k * 1024, 0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(Rz, (lds_ptr)(buf + BR::ZN), 16, vo,
+                                           tile * 4 * kTile * 8, 0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(Rc, (lds_ptr)(buf + BR::NBR), 16, vo,
+                                           tile * 4 * kTile * 4, 0, 0);
+}
+
+// exterior traces of one face at the lane's FK face-node rows
+template <int N>
+struct FaceIn {
+  static constexpr int FK = Dims3<N>::FK;
+  double p[FK], u[FK], v[FK], w[FK], rb[FK];
+};
+
+template <int N>
+__device__ __forceinline__ void face_fetch(FaceIn<N>& x, int f, int code, int e, Rsrc Rq, Rsrc Rb,
+                                           const int* smap, int g) {
+  using D = Dims3<N>;
+  constexpr int Np = D::Np, Nfp = D::Nfp, FK = D::FK;
+  constexpr unsigned FS = Np * kTile * 8, TS = 4 * FS;
+  const bool inner = code >= 0;
+  const int cb = -1 - code;
+  const bool hb = !inner && (cb & 3) == 0;
+  const int e2 = inner ? (code >> 5) : e;
+  const unsigned nb = (unsigned)(e2 >> 4) * TS + (unsigned)(e2 & 15) * 8;
+  const int mapbase = inner ? ((f * 4 + ((code >> 3) & 3)) * 6 + (code & 7)) * Nfp
+                            : ((f * 4) * 6 + ((cb >> 2) & 7)) * Nfp;
+  const unsigned qbo = (unsigned)(hb ? (cb >> 5) : 0) * (Nfp * 8);
+#pragma unroll
+  for (int jj = 0; jj < FK; ++jj) {
+    const int kc = min(4 * jj + g, Nfp - 1);
+    const int n2 = smap[mapbase + kc];
+    const unsigned oP = nb + (unsigned)n2 * (kTile * 8);
+    x.p[jj] = bld(Rq, oP, 0);
+    x.u[jj] = bld(Rq, oP, FS);
+    x.v[jj] = bld(Rq, oP, 2 * FS);
+    x.w[jj] = bld(Rq, oP, 3 * FS);
+    x.rb[jj] = bld(Rb, qbo + (unsigned)min(n2, Nfp - 1) * 8, 0);
+  }
+}
+
+// One work item whose tile is in buf; issues the loads of item `next` (if
+// >= 0) into buf once the tile's copy has been read.
+template <int N>
+__device__ __forceinline__ void tile_step_dma(const Lvl3& L, const double* __restrict__ qo,
+                                              double* __restrict__ qn, double* __restrict__ res,
+                                              const double* __restrict__ qb3, double A, double B,
+                                              double dt, const Shots& sh, long long item,
+                                              long long next, int ngrp, const int* smap,
+                                              const int* smask, const double* sops, char* buf,
+                                              int lane) {
+  using D = Dims3<N>;
+  using BR = BufR<N>;
+  constexpr int Np = D::Np, Nfp = D::Nfp, RG = D::RG, FK = D::FK;
+  constexpr unsigned FS = Np * kTile * 8;   // bytes between two fields of a tile
+  constexpr unsigned TS = 4 * FS;           // bytes per tile
+  const int shot = (int)(item / ngrp);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tile = (int)(item - (long long)shot * ngrp) * kWavesR + wv;
+  // the tile's direct loads have landed: vector memory operations complete
+  // in order and the previous tile issued 8 RG stores after them (the
+  // compiler does not order LDS reads after direct-to-LDS loads by itself)
+  constexpr int kVm = 8 * RG < 63 ? 8 * RG : 63;
+  __builtin_amdgcn_s_waitcnt((kVm & 15) | ((kVm >> 4) << 14) | (7 << 4) | (15 << 8));
+  if (tile >= L.ntile) {
+    // no stores follow: wait for the next tile's direct loads here
+    __builtin_amdgcn_s_waitcnt(0);
+    if (next >= 0) tile_dma<N>(L, qo, sh, next, ngrp, buf, lane);
+    __builtin_amdgcn_s_waitcnt(0);
+    return;
+  }
+  const double* qos = qo + shot * sh.st3;
+  double* qns = qn + shot * sh.st3;
+  double* ress = res + shot * sh.st3;
+  const double* qbs = qb3 + shot * sh.stb3;
+  const int es = lane & 15, g = lane >> 4;
+  const int ta = (lane & 3) + 4 * g;   // this lane's entry of a 16-value A fragment
+  const double* frag = sops + ta;
+  const double* fragL = frag + 3 * RG * RG * 16;
+  const int e = tile * kTile + es;
+  const unsigned nbytes = (unsigned)L.ntile * TS;
+  const Rsrc Rq = rsrc(qos, nbytes), Rn = rsrc(qns, nbytes), Rr = rsrc(ress, nbytes);
+  const Rsrc Rb = rsrc(qbs, (unsigned)L.nqb3 * 8);
+  const unsigned tb = (unsigned)tile * TS + (unsigned)es * 8;   // this lane's element
+  const double* bq = reinterpret_cast<const double*>(buf) + es;   // [field][node][16]
+  const double* bg = reinterpret_cast<const double*>(buf + BR::GEO) + es;
+  const double* bz = reinterpret_cast<const double*>(buf + BR::ZN) + es;
+  const int* bc = reinterpret_cast<const int*>(buf + BR::NBR) + es;
+  int fcode[4];
+  double fz[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    fcode[f] = bc[f * kTile];
+    fz[f] = bz[f * kTile];
+  }
+  // every face's exterior traces, in flight during the volume term
+  FaceIn<N> fb[4];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) face_fetch<N>(fb[f], f, fcode[f], e, Rq, Rb, smap, g);
+  const double rx = bg[0 * kTile], ry = bg[1 * kTile], rz = bg[2 * kTile];
+  const double sx = bg[3 * kTile], sy = bg[4 * kTile], sz = bg[5 * kTile];
+  const double tx = bg[6 * kTile], ty = bg[7 * kTile], tz = bg[8 * kTile];
+  const double irho = bg[9 * kTile], Kb = bg[10 * kTile], Z = bg[11 * kTile];
+  double qv[RG][4];
+#pragma unroll
+  for (int j = 0; j < RG; ++j) {
+    const int n = min(4 * j + g, Np - 1);
+#pragma unroll
+    for (int fl = 0; fl < 4; ++fl) qv[j][fl] = bq[(fl * Np + n) * kTile];
+  }
+
+  // ---- volume (as in tile_step), operands from registers
+  double dpr[RG], dps[RG], dpt[RG], dv[RG];
+#pragma unroll
+  for (int i = 0; i < RG; ++i) dpr[i] = dps[i] = dpt[i] = dv[i] = 0.0;
+#pragma unroll
+  for (int j = 0; j < RG; ++j) {
+    const double p = qv[j][0], u = qv[j][1], v = qv[j][2], w = qv[j][3];
+    const double fr = rx * u + ry * v + rz * w;
+    const double fs = sx * u + sy * v + sz * w;
+    const double ft = tx * u + ty * v + tz * w;
+    const double* fj = frag + j * 16;
+#pragma unroll
+    for (int i = 0; i < RG; ++i) {
+      const double ar = fj[((0 * RG + i) * RG) * 16];
+      const double as = fj[((1 * RG + i) * RG) * 16];
+      const double at = fj[((2 * RG + i) * RG) * 16];
+      dpr[i] = mfma4(ar, p, dpr[i]);
+      dps[i] = mfma4(as, p, dps[i]);
+      dpt[i] = mfma4(at, p, dpt[i]);
+      dv[i] = mfma4(ar, fr, dv[i]);
+      dv[i] = mfma4(as, fs, dv[i]);
+      dv[i] = mfma4(at, ft, dv[i]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RG; ++i) dv[i] *= -Kb;
+  double* rp = dv;
+
+  // ---- surface (as in tile_step); own traces from the LDS copy
+  double rv[RG][4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    __builtin_amdgcn_sched_barrier(0);
+    if (f == 1) {
+      // the residual of this tile, needed by the update
+#pragma unroll
+      for (int j = 0; j < RG; ++j) {
+        const unsigned o = tb + (unsigned)min(4 * j + g, Np - 1) * (kTile * 8);
+#pragma unroll
+        for (int fl = 0; fl < 4; ++fl) rv[j][fl] = bldn(Rr, o, fl * FS);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (f == 0) {
+      face_fetch<N>(fb[3], 3, fcode[3], e, Rq, Rb, smap, g);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const FaceIn<N>& x = fb[f];
+    const double cr = f == 2 ? 1.0 : (f == 3 ? -1.0 : 0.0);
+    const double cs = f == 2 ? 1.0 : (f == 1 ? -1.0 : 0.0);
+    const double ct = f == 2 ? 1.0 : (f == 0 ? -1.0 : 0.0);
+    double nx = cr * rx + cs * sx + ct * tx;
+    double ny = cr * ry + cs * sy + ct * ty;
+    double nz = cr * rz + cs * sz + ct * tz;
+    const double fsc = sqrt(nx * nx + ny * ny + nz * nz);
+    const double inv = 1.0 / fsc;
+    nx *= inv;
+    ny *= inv;
+    nz *= inv;
+    const int code = fcode[f];
+    const double ZP = fz[f];
+    const bool inner = code >= 0;
+    const int cb = -1 - code;
+    const bool hb = !inner && (cb & 3) == 0;
+    const bool dir = !inner && (cb & 3) == 2;
+    const double iZ = 1.0 / (Z + ZP);
+    const double aM = ZP * iZ, aP = Z * iZ, bZ = Z * aM;
+    const double cP = fsc * Kb;
+#pragma unroll
+    for (int jj = 0; jj < FK; ++jj) {
+      const int kc = min(4 * jj + g, Nfp - 1);
+      const int n = smask[f * Nfp + kc];
+      const double* sm = bq + n * kTile;
+      const double pM = sm[0], uM = sm[Np * kTile], vM = sm[2 * Np * kTile],
+                   wM = sm[3 * Np * kTile];
+      const double pP = x.p[jj], uP = x.u[jj], vP = x.v[jj], wP = x.w[jj];
+      const double unM = nx * uM + ny * vM + nz * wM;
+      const double unP = nx * uP + ny * vP + nz * wP;
+      const double pG = inner ? pP : (dir ? -pM : (hb ? 2.0 * x.rb[jj] : 0.0));
+      const double uG = inner ? unP : (dir ? unM : 0.0);
+      const double pF = aM * pM + aP * pG + bZ * (unM - uG);
+      const double unF = iZ * (pM - pG) + aP * unM + aM * uG;
+      const double fp = cP * (unM - unF);
+      const double fu = pM - pF;
+      const double* fl = fragL + (f * FK + jj) * 16;
+      if (f == 2) {
+#pragma unroll
+        for (int i = 0; i < RG; ++i) {
+          const double a = fl[i * 4 * FK * 16];
+          rp[i] = mfma4(a, fp, rp[i]);
+          dpr[i] = mfma4(a, -fu, dpr[i]);
+          dps[i] = mfma4(a, -fu, dps[i]);
+          dpt[i] = mfma4(a, -fu, dpt[i]);
+        }
+      } else {
+        double* G = f == 0 ? dpt : (f == 1 ? dps : dpr);
+#pragma unroll
+        for (int i = 0; i < RG; ++i) {
+          const double a = fl[i * 4 * FK * 16];
+          rp[i] = mfma4(a, fp, rp[i]);
+          G[i] = mfma4(a, fu, G[i]);
+        }
+      }
+    }
+  }
+  // point source S(tau) = amp (tau - t0) exp(-pi^2 f0^2 (tau - t0)^2) on its
+  // element (the branch is uniform: only the source's wave takes it)
+  {
+    const double* sp = sh.srcp + 4 * shot;
+    const bool src = (double)e == sp[0];
+    if (__builtin_amdgcn_read_exec() & __ballot(src)) {
+      const double tr = sh.tau - sp[2], ar = M_PI * sp[1] * tr;
+      const double src_s = sp[3] * tr * exp(-ar * ar);
+      const double* src_w = sh.srcw + (size_t)shot * Np;
+#pragma unroll
+      for (int i = 0; i < RG; ++i)
+        if (src) rp[i] += src_w[min(4 * i + g, Np - 1)] * src_s;
+    }
+  }
+  // the copy has been read: the next tile may land
+  __builtin_amdgcn_sched_barrier(0);
+  if (next >= 0) tile_dma<N>(L, qo, sh, next, ngrp, buf, lane);
+  __builtin_amdgcn_sched_barrier(0);
+
+  // ---- LSRK update from the registers: 8 RG stores, every lane issuing
+  // them (a lane without a row stores past the end of the resource, which
+  // the hardware drops), so the count after the direct loads is fixed
+  const bool live = irho != 0.0;
+#pragma unroll
+  for (int i = 0; i < RG; ++i) {
+    const int n = 4 * i + g;
+    const int nc = min(n, Np - 1);
+    const unsigned o = (live && n < Np) ? tb + (unsigned)nc * (kTile * 8) : 0xFFFFFFF8u;
+    const double a = dpr[i], bq_ = dps[i], c = dpt[i];
+    const double rhs[4] = {rp[i],
+                           -irho * (rx * a + sx * bq_ + tx * c),
+                           -irho * (ry * a + sy * bq_ + ty * c),
+                           -irho * (rz * a + sz * bq_ + tz * c)};
+#pragma unroll
+    for (int fl = 0; fl < 4; ++fl) {
+      const double rr = A * rv[i][fl] + dt * rhs[fl];
+      bstn(Rr, o, fl * FS, rr);
+      bstn(Rn, o, fl * FS, qv[i][fl] + B * rr);
+    }
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kWavesR * 64, 1) k_level3_dma(Lvl3 L, const double* __restrict__ qo,
+                                                       double* __restrict__ qn,
+                                                       double* __restrict__ res,
+                                                       const double* __restrict__ qb3, double A,
+                                                       double B, double dt, Shots sh) {
+  using D = Dims3<N>;
+  constexpr int Nfp = D::Nfp;
+  extern __shared__ double sfrag[];
+  int* smask = reinterpret_cast<int*>(sfrag);
+  int* smap = smask + 4 * Nfp;
+  constexpr int kTabDoubles = (4 * Nfp + 96 * Nfp + 1) / 2;
+  const int lane = threadIdx.x & 63;
+  const int ngrp = (L.ntile + kWavesR - 1) / kWavesR;
+  const XcdRange rg_(ngrp * (long long)sh.n);
+  double* sops = sfrag + kTabDoubles;
+  char* buf = reinterpret_cast<char*>(sops + D::NFRAG * 16) +
+              __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * BufR<N>::BYTES;
+  // the first tile's loads overlap the table fill
+  if (rg_.lo < rg_.hi) tile_dma<N>(L, qo, sh, rg_.lo, ngrp, buf, lane);
+  fill_lds<kWavesR * 64, 4 * Nfp>(smask, L.fmask, threadIdx.x);
+  fill_lds<kWavesR * 64, 96 * Nfp>(smap, L.fmap, threadIdx.x);
+  fill_lds<kWavesR * 64, D::NFRAG * 16>(sops, L.ops, threadIdx.x);
+  __syncthreads();
+  for (long long it = rg_.lo; it < rg_.hi; it += rg_.step) {
+    const long long nx = it + rg_.step;
+    tile_step_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, it, nx < rg_.hi ? nx : -1, ngrp, smap,
+                     smask, sops, buf, lane);
+  }
+}
+
 // -------------------------------------------------------------- energy ---
 // One block per tile; partial sum of J/2 (p M p / (rho c^2) + rho u M u),
 // accumulated in FP64 whatever the state's type.
@@ -381,8 +720,44 @@ __global__ void k_energy(Lvl3 L, const T* __restrict__ q, const double* __restri
 }
 
 template <int N>
-hipError_t launch3(const Lvl3& L, const double* qo, double* qn, double* res, const double* qb3,
-                   double A, double B, double dt, const Shots& sh, hipStream_t st) {
+hipError_t launch3_dma(const Lvl3& L, const double* qo, double* qn, double* res,
+                       const double* qb3, double A, double B, double dt, const Shots& sh,
+                       hipStream_t st) {
+  using D = Dims3<N>;
+  constexpr int Nfp = D::Nfp;
+  const size_t lds = sizeof(double) * ((4 * Nfp + 96 * Nfp + 1) / 2 + D::NFRAG * 16) +
+                     (size_t)kWavesR * BufR<N>::BYTES;
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_level3_dma<N>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int ngrp = (L.ntile + kWavesR - 1) / kWavesR;
+  if (sh.n < 1) return hipErrorInvalidValue;
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3_dma<N>, kWavesR * 64, lds);
+    if (e != hipSuccess) return e;
+    resident = std::max(1, per_cu) * prop.multiProcessorCount;
+  }
+  const long long items = (long long)ngrp * sh.n;
+  const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, items) / 8 * 8);
+  hipLaunchKernelGGL(k_level3_dma<N>, dim3(blocks), dim3(kWavesR * 64), lds, st, L, qo, qn, res,
+                     qb3, A, B, dt, sh);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch3_reg(const Lvl3& L, const double* qo, double* qn, double* res,
+                       const double* qb3, double A, double B, double dt, const Shots& sh,
+                       hipStream_t st) {
   using D = Dims3<N>;
   constexpr int Nfp = D::Nfp;
   const size_t lds = sizeof(double) * ((4 * Nfp + 96 * Nfp + 1) / 2 + (D::kLds ? D::NFRAG * 16 : 0));
@@ -413,6 +788,17 @@ hipError_t launch3(const Lvl3& L, const double* qo, double* qn, double* res, con
   hipLaunchKernelGGL(k_level3<N>, dim3(blocks), dim3(kWaves3 * 64), lds, st, L, qo, qn, res,
                      qb3, A, B, dt, sh);
   return hipGetLastError();
+}
+
+// N <= 4: the tile-on-chip kernel (its registers and LDS hold a whole
+// tile); N = 5, 6: the register-streaming kernel
+template <int N>
+hipError_t launch3(const Lvl3& L, const double* qo, double* qn, double* res, const double* qb3,
+                   double A, double B, double dt, const Shots& sh, hipStream_t st) {
+  if constexpr (N <= 4)
+    return launch3_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+  else
+    return launch3_reg<N>(L, qo, qn, res, qb3, A, B, dt, sh, st);
 }
 
 }  // namespace
