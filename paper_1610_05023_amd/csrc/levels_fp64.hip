@@ -348,14 +348,15 @@ __device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restric
 // The same stage for N <= 4 with one wave per SIMD (one workgroup of four
 // waves per CU).  Each wave owns an LDS buffer that receives its next tile
 // (state, geometry, impedances, face codes) by direct buffer-to-LDS loads,
-// issued once the surface term has read the current tile's copy and before
-// the update's stores, so the tile lands while the wave finishes the current
-// one.  The wave holds the tile's q in registers (the B-fragment rows a lane
-// holds for the volume term, nodes 4 j + g of element l%16, are the
-// D-fragment rows it updates), reads the own traces from the LDS copy, and
-// has the exterior traces of faces 0-2 in flight during the volume term (face
-// 3's during face 0), so each value of q and res crosses HBM once; the
-// neighbour traces are re-read, mostly from L2.
+// issued as soon as the surface term no longer reads the current tile's
+// copy (the own traces of the last face are taken into registers first), so
+// the tile lands while the wave finishes the current one.  The wave holds
+// the tile's q in registers (the B-fragment rows a lane holds for the volume
+// term, nodes 4 j + g of element l%16, are the D-fragment rows it updates),
+// reads the own traces from the LDS copy, and has the exterior traces of
+// faces 0-2 in flight during the volume term (face 3's during face 0), so
+// each value of q and res crosses HBM once; the neighbour traces are
+// re-read, mostly from L2.
 constexpr int kWavesR = 4;
 
 template <int N>
@@ -535,6 +536,8 @@ __device__ __forceinline__ void tile_step_dma(const Lvl3& L, const double* __res
 
   // ---- surface (as in tile_step); own traces from the LDS copy
   double rv[RG][4];
+  constexpr int kEarlyFace = 3;
+  double ownr[4 - kEarlyFace][FK][4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     __builtin_amdgcn_sched_barrier(0);
@@ -550,6 +553,22 @@ __device__ __forceinline__ void tile_step_dma(const Lvl3& L, const double* __res
     }
     if (f == 0) {
       face_fetch<N>(fb[3], 3, fcode[3], e, Rq, Rb, smap, g);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (f == kEarlyFace) {
+      // own traces of the remaining faces into registers; then the copy is
+      // free and the next tile's direct loads go out
+#pragma unroll
+      for (int f2 = kEarlyFace; f2 < 4; ++f2)
+#pragma unroll
+        for (int jj = 0; jj < FK; ++jj) {
+          const int n = smask[f2 * Nfp + min(4 * jj + g, Nfp - 1)];
+#pragma unroll
+          for (int fl = 0; fl < 4; ++fl) ownr[f2 - kEarlyFace][jj][fl] = bq[(fl * Np + n) * kTile];
+        }
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): every LDS read returned
+      __builtin_amdgcn_sched_barrier(0);
+      if (next >= 0) tile_dma<N>(L, qo, sh, next, ngrp, buf, lane);
       __builtin_amdgcn_sched_barrier(0);
     }
     const FaceIn<N>& x = fb[f];
@@ -575,11 +594,21 @@ __device__ __forceinline__ void tile_step_dma(const Lvl3& L, const double* __res
     const double cP = fsc * Kb;
 #pragma unroll
     for (int jj = 0; jj < FK; ++jj) {
-      const int kc = min(4 * jj + g, Nfp - 1);
-      const int n = smask[f * Nfp + kc];
-      const double* sm = bq + n * kTile;
-      const double pM = sm[0], uM = sm[Np * kTile], vM = sm[2 * Np * kTile],
-                   wM = sm[3 * Np * kTile];
+      double pM, uM, vM, wM;
+      if (f >= kEarlyFace) {
+        pM = ownr[f - kEarlyFace][jj][0];
+        uM = ownr[f - kEarlyFace][jj][1];
+        vM = ownr[f - kEarlyFace][jj][2];
+        wM = ownr[f - kEarlyFace][jj][3];
+      } else {
+        const int kc = min(4 * jj + g, Nfp - 1);
+        const int n = smask[f * Nfp + kc];
+        const double* sm = bq + n * kTile;
+        pM = sm[0];
+        uM = sm[Np * kTile];
+        vM = sm[2 * Np * kTile];
+        wM = sm[3 * Np * kTile];
+      }
       const double pP = x.p[jj], uP = x.u[jj], vP = x.v[jj], wP = x.w[jj];
       const double unM = nx * uM + ny * vM + nz * wM;
       const double unP = nx * uP + ny * vP + nz * wP;
@@ -624,10 +653,6 @@ __device__ __forceinline__ void tile_step_dma(const Lvl3& L, const double* __res
         if (src) rp[i] += src_w[min(4 * i + g, Np - 1)] * src_s;
     }
   }
-  // the copy has been read: the next tile may land
-  __builtin_amdgcn_sched_barrier(0);
-  if (next >= 0) tile_dma<N>(L, qo, sh, next, ngrp, buf, lane);
-  __builtin_amdgcn_sched_barrier(0);
 
   // ---- LSRK update from the registers: 8 RG stores, every lane issuing
   // them (a lane without a row stores past the end of the resource, which
