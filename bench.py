@@ -142,6 +142,8 @@ def main():
                     help="fp32: FP32 3D level on FP32 MFMA, FP64 boundary levels")
     ap.add_argument("--order", type=int, default=None, help="override the degree N")
     ap.add_argument("--habc", type=int, default=None, help="override the HABC order P")
+    ap.add_argument("--graph", action="store_true",
+                    help="replayed stepping: every step runs as one captured HIP graph")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run 1 GiB reference kernels first (for PMC byte counters)")
     args = ap.parse_args()
@@ -191,14 +193,23 @@ def main():
     print(f"[bench] setup {time.perf_counter() - t_setup:.1f} s; K={K} Ktri={k['Ktri']} "
           f"Klin={k['Klin']} unknowns={U}", file=sys.stderr, flush=True)
     dt = wl["dt"]
+    if args.graph:
+        s.set_graph(True)               # each step replays one captured HIP graph
     s.step(args.warmup, dt, 0.0)
     torch.cuda.synchronize()
-    s.kernel_timing(True)
+    if not args.graph:
+        s.kernel_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.step(args.steps, dt, args.warmup * dt)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    if args.graph:
+        # kernel durations come from HIP events around eager launches
+        s.set_graph(False)
+        s.kernel_timing(True)
+        s.step(20, dt, (args.warmup + args.steps) * dt)
+        torch.cuda.synchronize()
     ms3, n3 = s.kernel_time(3)
     s.kernel_timing(False)
     finite = all(s.check(shot=j)[0] == "DGH_OK" for j in range(nsh))
@@ -244,7 +255,8 @@ def main():
                     "shots": nsh}) | {
                    "K_tet": K, "K_tri": k["Ktri"], "K_lin": k["Klin"], "K_pnt": k["Kpnt"],
                    "N": wl["N"], "P": wl["P"], "unknowns": U, "dt": dt,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "step_mode": "hip graph per step" if args.graph else "eager launches"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,

@@ -149,6 +149,17 @@ dgh_status dgh_set_source(dgh_ctx* ctx, int shot, const double* xs, double f0, d
  * Asynchronous on the bound stream. */
 dgh_status dgh_step(dgh_ctx* ctx, int n_steps, double dt, double t_start);
 
+/* Replayed stepping: enable = 1 makes dgh_step capture one step (all its
+ * launches, for each of the two parities of the double-buffered states) in
+ * HIP graphs on a stream of the library's own, and replay one graph per
+ * step on the bound stream; the stage times then come from a device clock
+ * that dgh_step sets to t_start and every step advances, computed so that
+ * results equal eager stepping bitwise.  The graphs are re-captured when dt,
+ * the closure or the trace recording change, and dropped by enable = 0, a
+ * new workspace or dgh_destroy.  Kernel timing (dgh_kernel_timing) uses
+ * eager stepping. */
+dgh_status dgh_set_graph(dgh_ctx* ctx, int enable);
+
 /* FP64 energy sum_k J_k/2 (p^T M p/(rho c^2) + rho u^T M u) of the 3D fields
  * of one shot (the energy weights of Section 4.1).  Synchronises. */
 dgh_status dgh_energy(dgh_ctx* ctx, int shot, double* e);

@@ -40,6 +40,7 @@ _SIGS = {
     "dgh_read_fields": [C.c_void_p, C.c_int, C.c_void_p],
     "dgh_set_source": [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_double, C.c_double],
     "dgh_step": [C.c_void_p, C.c_int, C.c_double, C.c_double],
+    "dgh_set_graph": [C.c_void_p, C.c_int],
     "dgh_energy": [C.c_void_p, C.c_int, C.POINTER(C.c_double)],
     "dgh_check": [C.c_void_p, C.c_int, C.c_double, C.c_double, C.POINTER(C.c_double)],
     "dgh_set_closure": [C.c_void_p, C.c_void_p, C.c_int],
@@ -200,6 +201,10 @@ class Solver:
 
     def step(self, n_steps, dt, t_start=0.0):
         self._call("dgh_step", int(n_steps), float(dt), float(t_start))
+
+    def set_graph(self, enable=True):
+        """Replayed stepping: each step runs as one captured HIP graph."""
+        self._call("dgh_set_graph", 1 if enable else 0)
 
     def energy(self, shot=0):
         e = C.c_double()

@@ -27,7 +27,28 @@ __global__ void __launch_bounds__(256) k_nonfinite(ScanList s, int* __restrict__
   if (threadIdx.x == 0) flags[a * gridDim.x + blockIdx.x] = bad;
 }
 
+// Device clock of replayed stepping (one lane; plain vector stores).
+__global__ void k_clock_set(double* clk, double t0) {
+  if (threadIdx.x == 0) {
+    clk[0] = t0;
+    clk[1] = 0.0;
+  }
+}
+__global__ void k_clock_tick(double* clk) {
+  if (threadIdx.x == 0) clk[1] = clk[1] + 1.0;
+}
+
 }  // namespace
+
+hipError_t launch_clock_set(double* clk, double t0, hipStream_t st) {
+  hipLaunchKernelGGL(k_clock_set, dim3(1), dim3(64), 0, st, clk, t0);
+  return hipGetLastError();
+}
+
+hipError_t launch_clock_tick(double* clk, hipStream_t st) {
+  hipLaunchKernelGGL(k_clock_tick, dim3(1), dim3(64), 0, st, clk);
+  return hipGetLastError();
+}
 
 hipError_t launch_nonfinite(const ScanList& s, int* flags, hipStream_t st) {
   if (s.count <= 0) return hipSuccess;

@@ -39,6 +39,7 @@ struct Layout {
   Region q1[2], res1, qb2, q02, geo1, info1, trinode1, ops1, cji, cij, G, H;
   Region qb1, info0, nrm0, T, srcw, srcp, wlines, wcorners, flags, ops2f;
   Region mlpw, hist, csamp;   // learned closure: parameters, trace history, samples
+  Region clk;                 // device clock of replayed stepping {t0, steps}
   // per-shot strides (doubles) of the state arrays
   size_t st3 = 0, st2 = 0, stb3 = 0, st1 = 0, stb2 = 0, stb1 = 0;
   size_t e3 = 8;   // bytes per element of the 3D state (8 FP64, 4 FP32)
@@ -85,6 +86,14 @@ struct dgh_ctx {
   bool closure = false;               // learned closure replaces the face level
   bool record = false;                // keep the trace history for sampling
   dgh::LvlF LF{};
+  // replayed stepping: one captured step per starting buffer parity, valid
+  // for (gdt, gclosure, grecord); captured on a stream of the library's own
+  bool graph = false;
+  hipStream_t cap = nullptr;
+  hipGraph_t g[2] = {nullptr, nullptr};
+  hipGraphExec_t gx[2] = {nullptr, nullptr};
+  double gdt = 0.0;
+  bool gclosure = false, grecord = false;
 };
 
 namespace {
@@ -97,6 +106,8 @@ dgh_status fail(dgh_ctx* c, dgh_status s, const std::string& msg) {
 dgh_status hipfail(dgh_ctx* c, hipError_t e, const char* where) {
   return fail(c, DGH_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
+
+void drop_graphs(dgh_ctx* c);
 
 #define HIPCHECK(ctx, call)                                   \
   do {                                                        \
@@ -477,6 +488,7 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.mlpw, (size_t)dgh::kMlpParams * sizeof(float));
   L.add(L.hist, S * nnode * 10 * sizeof(float));
   L.add(L.csamp, nnode * 12 * sizeof(float));   // rows of 11, then targets
+  L.add(L.clk, 2 * sizeof(double));
 }
 
 template <class V>
@@ -706,6 +718,7 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
   if (!dev || bytes < c->lay.total) return fail(c, DGH_ENOMEM, "workspace too small");
   if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(c, DGH_EINVAL, "workspace not 256-byte aligned");
   HIPCHECK(c, hipSetDevice(c->device));
+  drop_graphs(c);   // captured steps hold the old workspace's addresses
   c->ws = static_cast<char*>(dev);
   c->stream = static_cast<hipStream_t>(stream);
   HostArrays h;
@@ -905,65 +918,152 @@ dgh_status dgh_set_source(dgh_ctx* c, int shot, const double* xs, double f0, dou
   return DGH_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One step (5 stages, Algorithm 1 order) on `st`.  Eager: the stage times
+// come from t; replayed (clk non-null): from the device clock, which the
+// step advances at its end.
+dgh_status enqueue_step(dgh_ctx* c, double dt, double t, hipStream_t st, double* clk) {
+  const Layout& L = c->lay;
+  dgh::Shots sh{c->n_shots, L.st3, L.st2, L.stb3, L.st1, L.stb2, L.stb1,
+                dptr<double>(c, L.srcw), dptr<double>(c, L.srcp), 0.0, clk, 0.0, dt};
+  const bool timed = c->timing && !clk;
+  for (int s = 0; s < 5; ++s) {
+    const int o = c->cur, n = 1 - c->cur;
+    sh.tau = t + kC[s] * dt;
+    sh.cs = kC[s];
+    if (timed) {
+      if (c->ev_used + 2 > c->ev.size()) {
+        for (int k = 0; k < 64; ++k) {
+          hipEvent_t e;
+          HIPCHECK(c, hipEventCreate(&e));
+          c->ev.push_back(e);
+        }
+      }
+      HIPCHECK(c, hipEventRecord(c->ev[c->ev_used], st));
+    }
+    if (L.e3 == 4)
+      HIPCHECK(c, dgh::launch_level3_f32(c->L3, dptr<float>(c, L.q3[o]), dptr<float>(c, L.q3[n]),
+                                         dptr<float>(c, L.res3), dptr<double>(c, L.qb3), kA[s],
+                                         kB[s], dt, sh, st));
+    else
+      HIPCHECK(c, dgh::launch_level3(c->L3, dptr<double>(c, L.q3[o]), dptr<double>(c, L.q3[n]),
+                                     dptr<double>(c, L.res3), dptr<double>(c, L.qb3), kA[s],
+                                     kB[s], dt, sh, st));
+    if (timed) {
+      HIPCHECK(c, hipEventRecord(c->ev[c->ev_used + 1], st));
+      c->ev_used += 2;
+    }
+    if (!c->closure) {   // with the closure, qb3 holds from the last step end
+      const dgh::FaceBufs fb{dptr<double>(c, L.q2[o]), dptr<double>(c, L.q2[n]),
+                             dptr<double>(c, L.res2), dptr<double>(c, L.qb3),
+                             dptr<double>(c, L.q03), c->ws + L.q3[n].off,
+                             dptr<double>(c, L.qb2), L.e3 == 4 ? 1 : 0};
+      HIPCHECK(c, dgh::launch_faces(c->LF, c->L2, fb, sh, kA[s], kB[s], dt, st));
+    }
+    HIPCHECK(c, dgh::launch_boundary(c->LB, c->L2, c->L1, c->L0, c->L3, dptr<double>(c, L.q2[o]),
+                                     dptr<double>(c, L.q2[n]), dptr<double>(c, L.res2),
+                                     dptr<double>(c, L.qb2), dptr<double>(c, L.qb3),
+                                     dptr<double>(c, L.q03), dptr<double>(c, L.q3[n]),
+                                     dptr<double>(c, L.q1[o]), dptr<double>(c, L.q1[n]),
+                                     dptr<double>(c, L.res1), dptr<double>(c, L.qb1),
+                                     dptr<double>(c, L.q02), kA[s], kB[s], dt, sh, st));
+    c->cur = n;
+  }
+  if (c->closure)
+    HIPCHECK(c, dgh::launch_closure(c->L2, dptr<float>(c, L.mlpw), c->ws + L.q3[c->cur].off,
+                                    L.e3 == 4 ? 1 : 0, c->mesh.tet.Np, dptr<float>(c, L.hist),
+                                    dptr<double>(c, L.qb3), dptr<double>(c, L.q03), sh, st));
+  else if (c->record)
+    HIPCHECK(c, dgh::launch_hist_push(c->L2, c->ws + L.q3[c->cur].off, L.e3 == 4 ? 1 : 0,
+                                      c->mesh.tet.Np, dptr<float>(c, L.hist), sh, st));
+  if (clk) HIPCHECK(c, dgh::launch_clock_tick(clk, st));
+  return DGH_OK;
+}
+
+void drop_graphs(dgh_ctx* c) {
+  for (int p = 0; p < 2; ++p) {
+    if (c->gx[p]) (void)hipGraphExecDestroy(c->gx[p]);
+    if (c->g[p]) (void)hipGraphDestroy(c->g[p]);
+    c->gx[p] = nullptr;
+    c->g[p] = nullptr;
+  }
+}
+
+// Captures one step for each starting buffer parity (5 stages flip the
+// double buffers, so consecutive steps alternate between the two graphs).
+dgh_status capture_steps(dgh_ctx* c, double dt) {
+  drop_graphs(c);
+  if (!c->cap) HIPCHECK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  const int saved = c->cur;
+  double* clk = dptr<double>(c, c->lay.clk);
+  for (int p = 0; p < 2; ++p) {
+    c->cur = p;
+    HIPCHECK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+    const dgh_status st = enqueue_step(c, dt, 0.0, c->cap, clk);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap, &g);
+    c->g[p] = g;
+    if (st != DGH_OK) {
+      c->cur = saved;
+      drop_graphs(c);
+      return st;
+    }
+    if (e != hipSuccess) {
+      c->cur = saved;
+      drop_graphs(c);
+      return hipfail(c, e, "hipStreamEndCapture");
+    }
+    const hipError_t ei = hipGraphInstantiate(&c->gx[p], g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      c->cur = saved;
+      drop_graphs(c);
+      return hipfail(c, ei, "hipGraphInstantiate");
+    }
+  }
+  c->cur = saved;
+  c->gdt = dt;
+  c->gclosure = c->closure;
+  c->grecord = c->record;
+  return DGH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
   if (!c) return DGH_EINVAL;
   if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "step before bind");
   if (n_steps < 0 || !(dt > 0) || !std::isfinite(t_start)) return fail(c, DGH_EINVAL, "bad step arguments");
-  const Layout& L = c->lay;
-  dgh::Shots sh{c->n_shots, L.st3, L.st2, L.stb3, L.st1, L.stb2, L.stb1,
-                dptr<double>(c, L.srcw), dptr<double>(c, L.srcp), 0.0};
-  for (int it = 0; it < n_steps; ++it) {
-    const double t = t_start + it * dt;
-    for (int s = 0; s < 5; ++s) {
-      const int o = c->cur, n = 1 - c->cur;
-      sh.tau = t + kC[s] * dt;
-      if (c->timing) {
-        if (c->ev_used + 2 > c->ev.size()) {
-          for (int k = 0; k < 64; ++k) {
-            hipEvent_t e;
-            HIPCHECK(c, hipEventCreate(&e));
-            c->ev.push_back(e);
-          }
-        }
-        HIPCHECK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
-      }
-      if (L.e3 == 4)
-        HIPCHECK(c, dgh::launch_level3_f32(c->L3, dptr<float>(c, L.q3[o]), dptr<float>(c, L.q3[n]),
-                                           dptr<float>(c, L.res3), dptr<double>(c, L.qb3), kA[s],
-                                           kB[s], dt, sh, c->stream));
-      else
-        HIPCHECK(c, dgh::launch_level3(c->L3, dptr<double>(c, L.q3[o]), dptr<double>(c, L.q3[n]),
-                                       dptr<double>(c, L.res3), dptr<double>(c, L.qb3), kA[s],
-                                       kB[s], dt, sh, c->stream));
-      if (c->timing) {
-        HIPCHECK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
-        c->ev_used += 2;
-      }
-      if (!c->closure) {   // with the closure, qb3 holds from the last step end
-        const dgh::FaceBufs fb{dptr<double>(c, L.q2[o]), dptr<double>(c, L.q2[n]),
-                               dptr<double>(c, L.res2), dptr<double>(c, L.qb3),
-                               dptr<double>(c, L.q03), c->ws + L.q3[n].off,
-                               dptr<double>(c, L.qb2), L.e3 == 4 ? 1 : 0};
-        HIPCHECK(c, dgh::launch_faces(c->LF, c->L2, fb, sh, kA[s], kB[s], dt, c->stream));
-      }
-      HIPCHECK(c, dgh::launch_boundary(c->LB, c->L2, c->L1, c->L0, c->L3, dptr<double>(c, L.q2[o]),
-                                       dptr<double>(c, L.q2[n]), dptr<double>(c, L.res2),
-                                       dptr<double>(c, L.qb2), dptr<double>(c, L.qb3),
-                                       dptr<double>(c, L.q03), dptr<double>(c, L.q3[n]),
-                                       dptr<double>(c, L.q1[o]), dptr<double>(c, L.q1[n]),
-                                       dptr<double>(c, L.res1), dptr<double>(c, L.qb1),
-                                       dptr<double>(c, L.q02), kA[s], kB[s], dt, sh, c->stream));
-      c->cur = n;
+  if (n_steps == 0) return DGH_OK;
+  if (c->graph && !c->timing) {
+    if (!c->gx[0] || c->gdt != dt || c->gclosure != c->closure || c->grecord != c->record) {
+      const dgh_status st = capture_steps(c, dt);
+      if (st != DGH_OK) return st;
     }
-    if (c->closure)
-      HIPCHECK(c, dgh::launch_closure(c->L2, dptr<float>(c, L.mlpw), c->ws + L.q3[c->cur].off,
-                                      L.e3 == 4 ? 1 : 0, c->mesh.tet.Np, dptr<float>(c, L.hist),
-                                      dptr<double>(c, L.qb3), dptr<double>(c, L.q03), sh,
-                                      c->stream));
-    else if (c->record)
-      HIPCHECK(c, dgh::launch_hist_push(c->L2, c->ws + L.q3[c->cur].off, L.e3 == 4 ? 1 : 0,
-                                        c->mesh.tet.Np, dptr<float>(c, L.hist), sh, c->stream));
+    double* clk = dptr<double>(c, c->lay.clk);
+    HIPCHECK(c, dgh::launch_clock_set(clk, t_start, c->stream));
+    for (int it = 0; it < n_steps; ++it) {
+      HIPCHECK(c, hipGraphLaunch(c->gx[c->cur], c->stream));
+      c->cur = 1 - c->cur;
+    }
+    return DGH_OK;
   }
+  for (int it = 0; it < n_steps; ++it) {
+    const dgh_status st = enqueue_step(c, dt, t_start + it * dt, c->stream, nullptr);
+    if (st != DGH_OK) return st;
+  }
+  return DGH_OK;
+}
+
+dgh_status dgh_set_graph(dgh_ctx* c, int enable) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "set_graph before bind");
+  c->graph = enable != 0;
+  if (!c->graph) drop_graphs(c);
   return DGH_OK;
 }
 
@@ -1145,6 +1245,8 @@ const char* dgh_last_error(const dgh_ctx* c) { return c ? c->err.c_str() : "null
 
 void dgh_destroy(dgh_ctx* c) {
   if (!c) return;
+  drop_graphs(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }

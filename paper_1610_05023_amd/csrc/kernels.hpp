@@ -4,6 +4,16 @@
 
 namespace dgh {
 
+// Stage time of a launch: given by value, or (replayed stepping) from the
+// device clock as (t0 + k dt) + cs dt, rounded exactly as the host computes
+// the eager value (no fused multiply-add), so both modes agree bitwise.
+template <class S>
+__device__ __forceinline__ double stage_time(const S& sh) {
+  if (!sh.clk) return sh.tau;
+  const double t = __dadd_rn(sh.clk[0], __dmul_rn(sh.clk[1], sh.dt));
+  return __dadd_rn(t, __dmul_rn(sh.cs, sh.dt));
+}
+
 // FP64 4x4x4 MFMA, four 4x4x4 blocks per instruction.
 __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);

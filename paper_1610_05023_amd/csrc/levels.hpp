@@ -109,8 +109,17 @@ struct Shots {
   size_t stb1;   // qb1
   const double* srcw;
   const double* srcp;
-  double tau;
+  double tau;          // stage time (eager stepping)
+  // replayed stepping: the stage time is clk[0] + clk[1] dt + cs dt, with
+  // clk = {t_start, steps done} on the device (null: use tau)
+  const double* clk;
+  double cs;
+  double dt;
 };
+
+// the device clock of replayed stepping: clk = {t0, 0}; clk[1] += 1
+hipError_t launch_clock_set(double* clk, double t0, hipStream_t st);
+hipError_t launch_clock_tick(double* clk, hipStream_t st);
 
 hipError_t launch_level3(const Lvl3& L, const double* qo, double* qn, double* res,
                          const double* qb3, double A, double B, double dt, const Shots& sh,

@@ -223,7 +223,7 @@ __device__ __forceinline__ void tile_f32(const Lvl3& L, const float* __restrict_
   const bool live = irho != 0.f;
   const double* sp = sh.srcp + 4 * shot;
   const bool src = (double)e == sp[0];
-  const double trr = sh.tau - sp[2], arr = M_PI * sp[1] * trr;
+  const double trr = stage_time(sh) - sp[2], arr = M_PI * sp[1] * trr;
   const float src_s = (float)(sp[3] * trr * exp(-arr * arr));
   const double* src_w = sh.srcw + (size_t)shot * Np;
 #pragma unroll

@@ -301,7 +301,7 @@ __device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restric
     // point source S(tau) = amp (tau - t0) exp(-pi^2 f0^2 (tau - t0)^2)
     const double* sp = sh.srcp + 4 * shot;
     const bool src = (double)e == sp[0];
-    const double tr = sh.tau - sp[2], ar = M_PI * sp[1] * tr;
+    const double tr = stage_time(sh) - sp[2], ar = M_PI * sp[1] * tr;
     const double src_s = sp[3] * tr * exp(-ar * ar);
     const double* src_w = sh.srcw + (size_t)shot * Np;
     constexpr int EC = 3;
@@ -645,7 +645,7 @@ __device__ __forceinline__ void tile_step_dma(const Lvl3& L, const double* __res
     const double* sp = sh.srcp + 4 * shot;
     const bool src = (double)e == sp[0];
     if (__builtin_amdgcn_read_exec() & __ballot(src)) {
-      const double tr = sh.tau - sp[2], ar = M_PI * sp[1] * tr;
+      const double tr = stage_time(sh) - sp[2], ar = M_PI * sp[1] * tr;
       const double src_s = sp[3] * tr * exp(-ar * ar);
       const double* src_w = sh.srcw + (size_t)shot * Np;
 #pragma unroll
