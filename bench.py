@@ -142,6 +142,8 @@ def main():
                     help="fp32: FP32 3D level on FP32 MFMA, FP64 boundary levels")
     ap.add_argument("--order", type=int, default=None, help="override the degree N")
     ap.add_argument("--habc", type=int, default=None, help="override the HABC order P")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the 3D launch candidates on this workload and keep the fastest")
     ap.add_argument("--graph", action="store_true",
                     help="replayed stepping: every step runs as one captured HIP graph")
     ap.add_argument("--calib-copy", action="store_true",
@@ -193,6 +195,12 @@ def main():
     print(f"[bench] setup {time.perf_counter() - t_setup:.1f} s; K={K} Ktri={k['Ktri']} "
           f"Klin={k['Klin']} unknowns={U}", file=sys.stderr, flush=True)
     dt = wl["dt"]
+    tuned = None
+    if args.autotune:
+        best, ms = s.autotune(10)
+        tuned = {"candidate": best, "ms_per_launch": [round(float(v), 4) for v in ms]}
+        print(f"[bench] autotune: candidate {best} of {list(np.round(ms, 4))} ms",
+              file=sys.stderr, flush=True)
     if args.graph:
         s.set_graph(True)               # each step replays one captured HIP graph
     s.step(args.warmup, dt, 0.0)
@@ -256,7 +264,8 @@ def main():
                    "K_tet": K, "K_tri": k["Ktri"], "K_lin": k["Klin"], "K_pnt": k["Kpnt"],
                    "N": wl["N"], "P": wl["P"], "unknowns": U, "dt": dt,
                    "parallelism": "single GPU",
-                   "step_mode": "hip graph per step" if args.graph else "eager launches"},
+                   "step_mode": "hip graph per step" if args.graph else "eager launches",
+                   "tuning": tuned if tuned is not None else "default (tile on chip, XCD ranges)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,

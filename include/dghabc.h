@@ -160,6 +160,21 @@ dgh_status dgh_step(dgh_ctx* ctx, int n_steps, double dt, double t_start);
  * eager stepping. */
 dgh_status dgh_set_graph(dgh_ctx* ctx, int enable);
 
+/* Launch tuning of the 3D level.  Candidates (dgh_tuning_count: 4 for FP64
+ * with N <= 4, else 2) are kernel * 2 + order: kernel 0 holds a whole tile
+ * on chip (FP64, N <= 4; the only kernel otherwise), kernel 1 streams it
+ * through registers; order 0 gives each of the 8 XCDs a contiguous range of
+ * tiles, order 1 deals tiles round-robin over all workgroups.  Every
+ * candidate computes the same step.  dgh_set_tuning forces a candidate;
+ * dgh_autotune times `launches` launches (1..10000) of each on the bound
+ * workload -- they read the current state and write only the other half of
+ * its double buffer, so the state is unchanged -- keeps the fastest, returns
+ * its index in *best and, if ms is not NULL, the milliseconds per launch of
+ * every candidate in ms[0..count-1].  Both synchronise. */
+dgh_status dgh_tuning_count(dgh_ctx* ctx, int* count);
+dgh_status dgh_set_tuning(dgh_ctx* ctx, int candidate);
+dgh_status dgh_autotune(dgh_ctx* ctx, int launches, int* best, double* ms);
+
 /* FP64 energy sum_k J_k/2 (p^T M p/(rho c^2) + rho u^T M u) of the 3D fields
  * of one shot (the energy weights of Section 4.1).  Synchronises. */
 dgh_status dgh_energy(dgh_ctx* ctx, int shot, double* e);

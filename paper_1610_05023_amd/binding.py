@@ -41,6 +41,9 @@ _SIGS = {
     "dgh_set_source": [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_double, C.c_double],
     "dgh_step": [C.c_void_p, C.c_int, C.c_double, C.c_double],
     "dgh_set_graph": [C.c_void_p, C.c_int],
+    "dgh_tuning_count": [C.c_void_p, C.POINTER(C.c_int)],
+    "dgh_set_tuning": [C.c_void_p, C.c_int],
+    "dgh_autotune": [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.c_void_p],
     "dgh_energy": [C.c_void_p, C.c_int, C.POINTER(C.c_double)],
     "dgh_check": [C.c_void_p, C.c_int, C.c_double, C.c_double, C.POINTER(C.c_double)],
     "dgh_set_closure": [C.c_void_p, C.c_void_p, C.c_int],
@@ -201,6 +204,23 @@ class Solver:
 
     def step(self, n_steps, dt, t_start=0.0):
         self._call("dgh_step", int(n_steps), float(dt), float(t_start))
+
+    def tuning_count(self):
+        n = C.c_int()
+        self._call("dgh_tuning_count", C.byref(n))
+        return n.value
+
+    def set_tuning(self, candidate):
+        self._call("dgh_set_tuning", int(candidate))
+
+    def autotune(self, launches=20):
+        """Times every launch candidate of the 3D level, keeps the fastest;
+        returns (best index, milliseconds per launch of each candidate)."""
+        n = self.tuning_count()
+        ms = np.zeros(n)
+        best = C.c_int()
+        self._call("dgh_autotune", int(launches), C.byref(best), _ptr(ms))
+        return best.value, ms
 
     def set_graph(self, enable=True):
         """Replayed stepping: each step runs as one captured HIP graph."""

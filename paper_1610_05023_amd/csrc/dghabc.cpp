@@ -1059,6 +1059,90 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
   return DGH_OK;
 }
 
+namespace {
+// tuning candidates: FP64 with N <= 4 has two 3D kernels x two item orders,
+// otherwise one kernel x two item orders; candidate = kernel * 2 + order
+int tuning_count(const dgh_ctx* c) { return (c->lay.e3 == 8 && c->N <= 4) ? 4 : 2; }
+}  // namespace
+
+dgh_status dgh_tuning_count(dgh_ctx* c, int* count) {
+  if (!c || !count) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "tuning before bind");
+  *count = tuning_count(c);
+  return DGH_OK;
+}
+
+dgh_status dgh_set_tuning(dgh_ctx* c, int candidate) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "tuning before bind");
+  if (candidate < 0 || candidate >= tuning_count(c)) return fail(c, DGH_EINVAL, "no such candidate");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  c->L3.kvar = candidate >> 1;
+  c->L3.order = candidate & 1;
+  drop_graphs(c);   // captured launches carry the old choice
+  return DGH_OK;
+}
+
+dgh_status dgh_autotune(dgh_ctx* c, int launches, int* best, double* ms) {
+  if (!c || !best) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "autotune before bind");
+  if (launches < 1 || launches > 10000) return fail(c, DGH_EINVAL, "launches out of range");
+  const Layout& L = c->lay;
+  const int nc = tuning_count(c), cur = c->cur;
+  // the 3D level of the first stage, reading the current state and writing
+  // only the other half of the double buffer (as its residual too), so the
+  // state is left as it was
+  dgh::Shots sh{c->n_shots, L.st3, L.st2, L.stb3, L.st1, L.stb2, L.stb1,
+                dptr<double>(c, L.srcw), dptr<double>(c, L.srcp), 0.0, nullptr, 0.0, 1e-6};
+  hipEvent_t e0, e1;
+  HIPCHECK(c, hipEventCreate(&e0));
+  HIPCHECK(c, hipEventCreate(&e1));
+  const int keep_kvar = c->L3.kvar, keep_order = c->L3.order;
+  double tbest = 0.0;
+  int ibest = -1;
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < nc && err == hipSuccess; ++k) {
+    c->L3.kvar = k >> 1;
+    c->L3.order = k & 1;
+    auto launch = [&]() {
+      if (L.e3 == 4)
+        return dgh::launch_level3_f32(c->L3, dptr<float>(c, L.q3[cur]), dptr<float>(c, L.q3[1 - cur]),
+                                      dptr<float>(c, L.q3[1 - cur]), dptr<double>(c, L.qb3),
+                                      kA[0], kB[0], 1e-6, sh, c->stream);
+      return dgh::launch_level3(c->L3, dptr<double>(c, L.q3[cur]), dptr<double>(c, L.q3[1 - cur]),
+                                dptr<double>(c, L.q3[1 - cur]), dptr<double>(c, L.qb3), kA[0],
+                                kB[0], 1e-6, sh, c->stream);
+    };
+    for (int w = 0; w < 2 && err == hipSuccess; ++w) err = launch();
+    if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
+    for (int r = 0; r < launches && err == hipSuccess; ++r) err = launch();
+    if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    if (err == hipSuccess) {
+      const double per = (double)t / launches;
+      if (ms) ms[k] = per;
+      if (ibest < 0 || per < tbest) {
+        tbest = per;
+        ibest = k;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) {
+    c->L3.kvar = keep_kvar;
+    c->L3.order = keep_order;
+    return hipfail(c, err, "autotune");
+  }
+  c->L3.kvar = ibest >> 1;
+  c->L3.order = ibest & 1;
+  drop_graphs(c);
+  *best = ibest;
+  return DGH_OK;
+}
+
 dgh_status dgh_set_graph(dgh_ctx* c, int enable) {
   if (!c) return DGH_EINVAL;
   if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "set_graph before bind");

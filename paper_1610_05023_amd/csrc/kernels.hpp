@@ -44,7 +44,14 @@ __device__ __forceinline__ void fill_lds(T* __restrict__ dst, const T* __restric
 // range [n x / 8, n (x + 1) / 8), so neighbouring items share an L2.
 struct XcdRange {
   long long lo, hi, step;
-  __device__ XcdRange(long long n) {
+  // plain != 0: round-robin over all blocks instead (item b, b + grid, ...)
+  __device__ XcdRange(long long n, int plain = 0) {
+    if (plain) {
+      lo = blockIdx.x;
+      hi = n;
+      step = gridDim.x;
+      return;
+    }
     const int x = blockIdx.x & 7;
     const int per = (gridDim.x + 7 - x) >> 3;   // blocks on XCD x
     lo = n * x / 8 + (blockIdx.x >> 3);

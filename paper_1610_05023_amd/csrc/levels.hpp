@@ -47,6 +47,8 @@ struct Lvl3 {
   const double* geo;
   const double* zn;
   const int* nbr;
+  int kvar;    // FP64 3D kernel for N <= 4: 0 tile on chip, 1 register-streaming
+  int order;   // work items: 0 XCD-contiguous ranges, 1 round-robin over blocks
 };
 
 // 2D level (faces).  q2 [Ktri][P][3][Np2]; geo [Ktri][8]: rx ry sx sy 1/rho

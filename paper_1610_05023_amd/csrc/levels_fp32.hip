@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(kWaves3f * 64, 2) k_level3_f32(Lvl3 L, const f
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int ngrp = (L.ntile + kWaves3f - 1) / kWaves3f;
-  const XcdRange rg_(ngrp * (long long)sh.n);
+  const XcdRange rg_(ngrp * (long long)sh.n, L.order);
   for (long long item = rg_.lo; item < rg_.hi; item += rg_.step)
     tile_f32<N>(L, qo, qn, res, qb3, A, B, dt, sh, item, ngrp, smap, smask, sops, lane);
 }

@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double
   // persistent: the workgroup loads its tables once, then its waves take
   // (shot, group of kWaves3 tiles) items from its XCD's range
   const int ngrp = (L.ntile + kWaves3 - 1) / kWaves3;
-  const XcdRange rg_(ngrp * (long long)sh.n);
+  const XcdRange rg_(ngrp * (long long)sh.n, L.order);
   for (long long item = rg_.lo; item < rg_.hi; item += rg_.step)
     tile_step<N>(L, qo, qn, res, qb3, A, B, dt, sh, item, ngrp, smap, smask, sops, lane);
 }
@@ -691,7 +691,7 @@ __global__ void __launch_bounds__(kWavesR * 64, 1) k_level3_dma(Lvl3 L, const do
   constexpr int kTabDoubles = (4 * Nfp + 96 * Nfp + 1) / 2;
   const int lane = threadIdx.x & 63;
   const int ngrp = (L.ntile + kWavesR - 1) / kWavesR;
-  const XcdRange rg_(ngrp * (long long)sh.n);
+  const XcdRange rg_(ngrp * (long long)sh.n, L.order);
   double* sops = sfrag + kTabDoubles;
   char* buf = reinterpret_cast<char*>(sops + D::NFRAG * 16) +
               __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * BufR<N>::BYTES;
@@ -816,14 +816,15 @@ hipError_t launch3_reg(const Lvl3& L, const double* qo, double* qn, double* res,
 }
 
 // N <= 4: the tile-on-chip kernel (its registers and LDS hold a whole
-// tile); N = 5, 6: the register-streaming kernel
+// tile) unless tuning chose the other; N = 5, 6: the register-streaming
+// kernel
 template <int N>
 hipError_t launch3(const Lvl3& L, const double* qo, double* qn, double* res, const double* qb3,
                    double A, double B, double dt, const Shots& sh, hipStream_t st) {
-  if constexpr (N <= 4)
-    return launch3_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, st);
-  else
-    return launch3_reg<N>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+  if constexpr (N <= 4) {
+    if (L.kvar == 0) return launch3_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+  }
+  return launch3_reg<N>(L, qo, qn, res, qb3, A, B, dt, sh, st);
 }
 
 }  // namespace

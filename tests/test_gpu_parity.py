@@ -233,3 +233,35 @@ def test_graph_replay_equals_eager(precision):
         for a in runs[0][k]:
             assert np.array_equal(runs[0][k][a], runs[1][k][a]), (precision, k, a)
     print(f"[graph] precision {precision}: replayed == eager bitwise", flush=True)
+
+
+def test_tuning_candidates_and_autotune():
+    """Every launch candidate of the 3D level (tile on chip / register
+    streaming x XCD ranges / round robin) matches the oracle on a layered
+    medium with a source and mixed faces; autotune leaves the state as it
+    was and picks one of them."""
+    n, N, P, steps, dt = 5, 4, 3, 6, 1e-3
+    case = make_case(n=n, N=N, P=P, medium="layered", init="random", seed=57,
+                     source=((0.41, 0.52, 0.33), 6.0, 0.02))
+    ref = run_oracle(case, steps, dt)
+    s = make_solver(case)
+    count = s.tuning_count()
+    assert count == 4
+    for cand in range(count):
+        s.set_state(case["state"])
+        s.set_tuning(cand)
+        s.step(steps, dt)
+        err = rel_errors(s.read_fields(), ref)
+        print(f"[tuning] candidate {cand}: max error {max(err.values()):.1e}", flush=True)
+        assert max(err.values()) <= TOL, (cand, err)
+    s.set_state(case["state"])
+    before = s.read_fields()
+    best, ms = s.autotune(5)
+    after = s.read_fields()
+    for a in before:
+        assert np.array_equal(before[a], after[a]), a
+    assert 0 <= best < count and np.all(ms > 0) and ms[best] == ms.min()
+    s.step(steps, dt)
+    err = rel_errors(s.read_fields(), ref)
+    print(f"[tuning] autotune picked {best}, ms/launch {np.round(ms, 4)}", flush=True)
+    assert max(err.values()) <= TOL, err
