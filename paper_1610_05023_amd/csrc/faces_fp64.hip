@@ -16,6 +16,8 @@
 // r- = (1/M) sum_i g_i p*_i -> qb3, S = r+ + r- -> q0_3, p_i = p*_i + S.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "levels.hpp"
 
@@ -34,39 +36,35 @@ struct Dims2 {
   static constexpr int NFRAG = 2 * RG * RG + RG * 3 * EK;
 };
 
-// T3: type of the 3D state (double, or float for the FP32 3D variant).
+// One work item: the kWaves2 wave slots of group bx of shot k (each wave
+// its TW triangles).  T3: type of the 3D state (double, or float for the
+// FP32 3D variant).
 template <int N, class T3>
-__global__ void __launch_bounds__(kWaves2 * 64, 2) k_faces(LvlF F, Lvl2 L2, FaceBufs b, Shots sh,
-                                                           double A, double B, double dt) {
+__device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBufs b,
+                                           const Shots& sh, double A, double B, double dt,
+                                           int bx, int k, const double* sops, const double* sg,
+                                           const int* smask,
+                                           double (*sbuf)[2][16 * 3 * Dims2<N>::Np]) {
   using D = Dims2<N>;
   constexpr int Np = D::Np, Nfp = D::Nfp, RG = D::RG, EK = D::EK;
   constexpr int SPAN = 16 * 3 * Np;          // fields of at most 16 (triangle, set) pairs
   constexpr int KL = (SPAN + 63) / 64;       // linear loads per lane
-  __shared__ double sops[D::NFRAG * 16];
-  __shared__ double sg[16];
-  __shared__ int smask[3 * Nfp];
-  __shared__ double sbuf[kWaves2][2][SPAN];  // per wave: q2 and res2 of its pairs
-  fill_lds<kWaves2 * 64, D::NFRAG * 16>(sops, F.ops, threadIdx.x);
-  fill_lds<kWaves2 * 64, 3 * Nfp>(smask, L2.fmask, threadIdx.x);
   const int P = L2.P;
-  if (threadIdx.x < P) sg[threadIdx.x] = L2.gamma[threadIdx.x];
-  __syncthreads();
   {
-    const size_t k = blockIdx.y;   // this block's shot
     b.q2o += k * sh.st2;
     b.q2n += k * sh.st2;
     b.res2 += k * sh.st2;
     b.qb3 += k * sh.stb3;
     b.q03 += k * sh.stb3;
     b.q3n = static_cast<const T3*>(b.q3n) + k * sh.st3;
-    b.qb2 += k * sh.stb2;
+    b.qb2 += (size_t)k * sh.stb2;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int es = lane & 15, g = lane >> 4;
   const int ta = (lane & 3) + 4 * g;         // lane's entry of an A fragment
   const int Pc = P > 0 ? P : 1, TW = 16 / Pc;
   const int tl = es / Pc, i = es - tl * Pc;
-  const int w0 = (blockIdx.x * kWaves2 + wv) * TW;   // first triangle of this wave
+  const int w0 = (bx * kWaves2 + wv) * TW;           // first triangle of this wave
   if (w0 >= L2.Kt) return;
   const int ntw = min(TW, L2.Kt - w0);               // triangles of this wave
   const bool col = tl < ntw;                         // column holds (triangle, set)
@@ -277,14 +275,57 @@ __global__ void __launch_bounds__(kWaves2 * 64, 2) k_faces(LvlF F, Lvl2 L2, Face
   }
 }
 
+// Persistent: each workgroup loads the operator fragments, face masks and
+// gamma into LDS once, then takes (shot, group) items from its XCD's range.
+template <int N, class T3>
+__global__ void __launch_bounds__(kWaves2 * 64, 2) k_faces(LvlF F, Lvl2 L2, FaceBufs b, Shots sh,
+                                                           double A, double B, double dt,
+                                                           int ngrp) {
+  using D = Dims2<N>;
+  constexpr int Np = D::Np, Nfp = D::Nfp;
+  __shared__ double sops[D::NFRAG * 16];
+  __shared__ double sg[16];
+  __shared__ int smask[3 * Nfp];
+  __shared__ double sbuf[kWaves2][2][16 * 3 * Np];  // per wave: q2 and res2 of its pairs
+  fill_lds<kWaves2 * 64, D::NFRAG * 16>(sops, F.ops, threadIdx.x);
+  fill_lds<kWaves2 * 64, 3 * Nfp>(smask, L2.fmask, threadIdx.x);
+  if (threadIdx.x < L2.P) sg[threadIdx.x] = L2.gamma[threadIdx.x];
+  __syncthreads();
+  const XcdRange rg_((long long)ngrp * sh.n);
+  for (long long it = rg_.lo; it < rg_.hi; it += rg_.step) {
+    const int k = (int)(it / ngrp), bx = (int)(it - (long long)k * ngrp);
+    faces_item<N, T3>(F, L2, b, sh, A, B, dt, bx, k, sops, sg, smask, sbuf);
+  }
+}
+
+template <int N, class T3>
+hipError_t launch_faces_t(const LvlF& F, const Lvl2& L2, const FaceBufs& b, const Shots& sh,
+                          double A, double B, double dt, int ngrp, hipStream_t st) {
+  // persistent grid: as many workgroups as fit on the device at once (a
+  // multiple of 8, so that every XCD has blocks for its range)
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_faces<N, T3>, kWaves2 * 64, 0);
+    if (e != hipSuccess) return e;
+    resident = std::max(1, per_cu) * prop.multiProcessorCount;
+  }
+  const long long items = (long long)ngrp * sh.n;
+  const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, items) / 8 * 8);
+  hipLaunchKernelGGL((k_faces<N, T3>), dim3(blocks), dim3(kWaves2 * 64), 0, st, F, L2, b, sh, A,
+                     B, dt, ngrp);
+  return hipGetLastError();
+}
+
 template <int N>
 hipError_t launch_faces_n(const LvlF& F, const Lvl2& L2, const FaceBufs& b, const Shots& sh,
-                          double A, double B, double dt, dim3 grid, dim3 block, hipStream_t st) {
-  if (b.q3f32)
-    hipLaunchKernelGGL((k_faces<N, float>), grid, block, 0, st, F, L2, b, sh, A, B, dt);
-  else
-    hipLaunchKernelGGL((k_faces<N, double>), grid, block, 0, st, F, L2, b, sh, A, B, dt);
-  return hipGetLastError();
+                          double A, double B, double dt, int ngrp, hipStream_t st) {
+  if (b.q3f32) return launch_faces_t<N, float>(F, L2, b, sh, A, B, dt, ngrp, st);
+  return launch_faces_t<N, double>(F, L2, b, sh, A, B, dt, ngrp, st);
 }
 
 }  // namespace
@@ -295,14 +336,14 @@ hipError_t launch_faces(const LvlF& F, const Lvl2& L2, const FaceBufs& b, const 
   if (L2.P > 16 || sh.n < 1 || sh.n > 65535) return hipErrorInvalidValue;
   const int TW = 16 / (L2.P > 0 ? L2.P : 1);
   const int waves = (L2.Kt + TW - 1) / TW;
-  const dim3 grid((waves + kWaves2 - 1) / kWaves2, sh.n), block(kWaves2 * 64);
+  const int ngrp = (waves + kWaves2 - 1) / kWaves2;
   switch (L2.Np) {
-    case 3: return launch_faces_n<1>(F, L2, b, sh, A, B, dt, grid, block, st);
-    case 6: return launch_faces_n<2>(F, L2, b, sh, A, B, dt, grid, block, st);
-    case 10: return launch_faces_n<3>(F, L2, b, sh, A, B, dt, grid, block, st);
-    case 15: return launch_faces_n<4>(F, L2, b, sh, A, B, dt, grid, block, st);
-    case 21: return launch_faces_n<5>(F, L2, b, sh, A, B, dt, grid, block, st);
-    case 28: return launch_faces_n<6>(F, L2, b, sh, A, B, dt, grid, block, st);
+    case 3: return launch_faces_n<1>(F, L2, b, sh, A, B, dt, ngrp, st);
+    case 6: return launch_faces_n<2>(F, L2, b, sh, A, B, dt, ngrp, st);
+    case 10: return launch_faces_n<3>(F, L2, b, sh, A, B, dt, ngrp, st);
+    case 15: return launch_faces_n<4>(F, L2, b, sh, A, B, dt, ngrp, st);
+    case 21: return launch_faces_n<5>(F, L2, b, sh, A, B, dt, ngrp, st);
+    case 28: return launch_faces_n<6>(F, L2, b, sh, A, B, dt, ngrp, st);
     default: return hipErrorInvalidValue;
   }
 }
