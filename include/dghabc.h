@@ -160,10 +160,10 @@ dgh_status dgh_step(dgh_ctx* ctx, int n_steps, double dt, double t_start);
  * eager stepping. */
 dgh_status dgh_set_graph(dgh_ctx* ctx, int enable);
 
-/* Launch tuning of the 3D level.  Candidates (dgh_tuning_count: 4 for FP64
- * with N <= 4, else 2) are kernel * 2 + order: kernel 0 holds a whole tile
- * on chip (FP64, N <= 4; the only kernel otherwise), kernel 1 streams it
- * through registers; order 0 gives each of the 8 XCDs a contiguous range of
+/* Launch tuning of the 3D level.  Candidates (dgh_tuning_count: 4 for
+ * N <= 4, else 2) are kernel * 2 + order: kernel 0 holds a whole tile on
+ * chip (N <= 4; the only kernel for N = 5, 6), kernel 1 streams it through
+ * registers; order 0 gives each of the 8 XCDs a contiguous range of
  * tiles, order 1 deals tiles round-robin over all workgroups.  Every
  * candidate computes the same step.  dgh_set_tuning forces a candidate;
  * dgh_autotune times `launches` launches (1..10000) of each on the bound

@@ -1060,9 +1060,9 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
 }
 
 namespace {
-// tuning candidates: FP64 with N <= 4 has two 3D kernels x two item orders,
-// otherwise one kernel x two item orders; candidate = kernel * 2 + order
-int tuning_count(const dgh_ctx* c) { return (c->lay.e3 == 8 && c->N <= 4) ? 4 : 2; }
+// tuning candidates: N <= 4 has two 3D kernels x two item orders, N = 5, 6
+// one kernel x two item orders; candidate = kernel * 2 + order
+int tuning_count(const dgh_ctx* c) { return c->N <= 4 ? 4 : 2; }
 }  // namespace
 
 dgh_status dgh_tuning_count(dgh_ctx* c, int* count) {

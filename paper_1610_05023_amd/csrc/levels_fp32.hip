@@ -285,9 +285,395 @@ __global__ void __launch_bounds__(kWaves3f * 64, 2) k_level3_f32(Lvl3 L, const f
     tile_f32<N>(L, qo, qn, res, qb3, A, B, dt, sh, item, ngrp, smap, smask, sops, lane);
 }
 
+// ------------------------------------------------- FP32, tile on chip ---
+// N <= 4: one workgroup of four waves per CU (one per SIMD).  Each wave's
+// LDS buffer receives its next tile (FP32 state, geometry, impedances, face
+// codes) by direct buffer-to-LDS loads, issued once the current tile's copy
+// has been read for the last time (before the last face), so every value
+// of q and res crosses HBM once; the wait at the start of a tile leaves the
+// previous update's stores in flight (they follow the direct loads).
+constexpr int kWavesF = 4;
+
+template <int N>
+struct BufF {
+  static constexpr int Np = Dims3f<N>::Np;
+  static constexpr int QK = (Np * 256 + 1023) / 1024;   // 1 KB loads for the state
+  static constexpr int QB = QK * 1024;
+  static constexpr int GEO = QB, ZN = QB + 2048, NBR = QB + 3072;
+  static constexpr int BYTES = QB + 4096;
+};
+
+typedef __attribute__((address_space(3))) void* lds_ptr_f;
+
+template <int N>
+__device__ __forceinline__ void tile_dma_f(const Lvl3& L, const float* __restrict__ qo,
+                                           const Shots& sh, long long item, int ngrp, char* buf,
+                                           int lane) {
+  using D = Dims3f<N>;
+  using BR = BufF<N>;
+  constexpr unsigned TS = 4 * D::Np * kTile * 4;
+  const int shot = (int)(item / ngrp);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tile = min((int)(item - (long long)shot * ngrp) * kWavesF + wv, L.ntile - 1);
+  const Rsrc Rq = rsrc(qo + shot * sh.st3, (unsigned)L.ntile * TS);
+  const Rsrc Rg = rsrc(L.geo, (unsigned)L.ntile * 12 * kTile * 8);
+  const Rsrc Rz = rsrc(L.zn, (unsigned)L.ntile * 4 * kTile * 8);
+  const Rsrc Rc = rsrc(L.nbr, (unsigned)L.ntile * 4 * kTile * 4);
+  const int vo = lane * 16;
+#pragma unroll
+  for (int k = 0; k < BR::QK; ++k)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(Rq, (lds_ptr_f)(buf + k * 1024), 16, vo,
+                                             (int)((unsigned)tile * TS + k * 1024), 0, 0);
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(Rg, (lds_ptr_f)(buf + BR::GEO + k * 1024), 16, vo,
+                                             tile * 12 * kTile * 8 + k * 1024, 0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(Rz, (lds_ptr_f)(buf + BR::ZN), 16, vo,
+                                           tile * 4 * kTile * 8, 0, 0);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(Rc, (lds_ptr_f)(buf + BR::NBR), 16, vo,
+                                           tile * 4 * kTile * 4, 0, 0);
+}
+
+template <int N>
+struct FaceInF {
+  static constexpr int FK = Dims3f<N>::FK;
+  float p[FK], u[FK], v[FK], w[FK], rb[FK];
+};
+
+template <int N>
+__device__ __forceinline__ void face_fetch_f(FaceInF<N>& x, int f, int code, int e, Rsrc Rq,
+                                             const double* __restrict__ qb3, const int* smap,
+                                             int g) {
+  using D = Dims3f<N>;
+  constexpr int Np = D::Np, Nfp = D::Nfp, FK = D::FK;
+  constexpr unsigned FS = Np * kTile * 4, TS = 4 * FS;
+  const bool inner = code >= 0;
+  const int cb = -1 - code;
+  const bool hb = !inner && (cb & 3) == 0;
+  const int e2 = inner ? (code >> 5) : e;
+  const unsigned nb = (unsigned)(e2 >> 4) * TS + (unsigned)(e2 & 15) * 4;
+  const int mapbase = inner ? ((f * 4 + ((code >> 3) & 3)) * 6 + (code & 7)) * Nfp
+                            : ((f * 4) * 6 + ((cb >> 2) & 7)) * Nfp;
+  const double* qbt = qb3 + (size_t)(hb ? (cb >> 5) : 0) * Nfp;
+#pragma unroll
+  for (int jj = 0; jj < FK; ++jj) {
+    const int kc = min(4 * jj + g, Nfp - 1);
+    const int n2 = smap[mapbase + kc];
+    const unsigned oP = nb + (unsigned)n2 * (kTile * 4);
+    x.p[jj] = fld(Rq, oP, 0);
+    x.u[jj] = fld(Rq, oP, FS);
+    x.v[jj] = fld(Rq, oP, 2 * FS);
+    x.w[jj] = fld(Rq, oP, 3 * FS);
+    x.rb[jj] = (float)qbt[min(n2, Nfp - 1)];
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void tile_f32_dma(const Lvl3& L, const float* __restrict__ qo,
+                                             float* __restrict__ qn, float* __restrict__ res,
+                                             const double* __restrict__ qb3, float A, float B,
+                                             float dt, const Shots& sh, long long item,
+                                             long long next, int ngrp, const int* smap,
+                                             const int* smask, const float* sops, char* buf,
+                                             int lane) {
+  using D = Dims3f<N>;
+  using BR = BufF<N>;
+  constexpr int Np = D::Np, Nfp = D::Nfp, RG = D::RG, RB = D::RB, FK = D::FK;
+  constexpr unsigned FS = Np * kTile * 4;   // bytes between two fields of a tile
+  constexpr unsigned TS = 4 * FS;           // bytes per tile
+  const int shot = (int)(item / ngrp);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tile = (int)(item - (long long)shot * ngrp) * kWavesF + wv;
+  // the tile's direct loads have landed: vector memory operations complete in
+  // order and the previous tile issued 32 RB stores after them (the compiler
+  // does not order LDS reads after direct-to-LDS loads by itself)
+  constexpr int kVm = 32 * RB < 63 ? 32 * RB : 63;
+  __builtin_amdgcn_s_waitcnt((kVm & 15) | ((kVm >> 4) << 14) | (7 << 4) | (15 << 8));
+  if (tile >= L.ntile) {
+    // no stores follow: wait for the next tile's direct loads here
+    __builtin_amdgcn_s_waitcnt(0);
+    if (next >= 0) tile_dma_f<N>(L, qo, sh, next, ngrp, buf, lane);
+    __builtin_amdgcn_s_waitcnt(0);
+    return;
+  }
+  const float* qos = qo + shot * sh.st3;
+  float* qns = qn + shot * sh.st3;
+  float* ress = res + shot * sh.st3;
+  const double* qbs = qb3 + shot * sh.stb3;
+  const int es = lane & 15, g = lane >> 4;
+  const float* frag = sops + lane;
+  const float* fragL = frag + 3 * RB * RG * 64;
+  const int e = tile * kTile + es;
+  const unsigned nbytes = (unsigned)L.ntile * TS;
+  const Rsrc Rq = rsrc(qos, nbytes), Rn = rsrc(qns, nbytes), Rr = rsrc(ress, nbytes);
+  const unsigned tb = (unsigned)tile * TS + (unsigned)es * 4;   // this lane's element
+  const float* bq = reinterpret_cast<const float*>(buf) + es;    // [field][node][16]
+  const double* bg = reinterpret_cast<const double*>(buf + BR::GEO) + es;
+  const double* bz = reinterpret_cast<const double*>(buf + BR::ZN) + es;
+  const int* bc = reinterpret_cast<const int*>(buf + BR::NBR) + es;
+  int fcode[4];
+  float fz[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    fcode[f] = bc[f * kTile];
+    fz[f] = (float)bz[f * kTile];
+  }
+  FaceInF<N> fb[4];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) face_fetch_f<N>(fb[f], f, fcode[f], e, Rq, qbs, smap, g);
+  const float rx = (float)bg[0 * kTile], ry = (float)bg[1 * kTile], rz = (float)bg[2 * kTile];
+  const float sx = (float)bg[3 * kTile], sy = (float)bg[4 * kTile], sz = (float)bg[5 * kTile];
+  const float tx = (float)bg[6 * kTile], ty = (float)bg[7 * kTile], tz = (float)bg[8 * kTile];
+  const float irho = (float)bg[9 * kTile], Kb = (float)bg[10 * kTile], Z = (float)bg[11 * kTile];
+
+  // ---- volume (as in tile_f32), B operands from the LDS copy
+  f4 dpr[RB], dps[RB], dpt[RB], dv[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) dpr[b] = dps[b] = dpt[b] = dv[b] = f4{0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < RG; ++j) {
+    const int n = min(4 * j + g, Np - 1);
+    const float p = bq[n * kTile], u = bq[(Np + n) * kTile], v = bq[(2 * Np + n) * kTile],
+                w = bq[(3 * Np + n) * kTile];
+    const float fr = rx * u + ry * v + rz * w;
+    const float fs = sx * u + sy * v + sz * w;
+    const float ft = tx * u + ty * v + tz * w;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const float ar = frag[((0 * RB + b) * RG + j) * 64];
+      const float as = frag[((1 * RB + b) * RG + j) * 64];
+      const float at = frag[((2 * RB + b) * RG + j) * 64];
+      dpr[b] = mfma16(ar, p, dpr[b]);
+      dps[b] = mfma16(as, p, dps[b]);
+      dpt[b] = mfma16(at, p, dpt[b]);
+      dv[b] = mfma16(ar, fr, dv[b]);
+      dv[b] = mfma16(as, fs, dv[b]);
+      dv[b] = mfma16(at, ft, dv[b]);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < RB; ++b) dv[b] *= -Kb;
+  f4* rp = dv;
+
+  // ---- surface (as in tile_f32); own traces from the LDS copy
+  float rv[RB][4][4], qd[RB][4][4], own3[FK][4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    __builtin_amdgcn_sched_barrier(0);
+    if (f == 0) {
+      face_fetch_f<N>(fb[3], 3, fcode[3], e, Rq, qbs, smap, g);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (f == 1) {
+      // the residual of this tile at the update's rows
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const unsigned o = tb + (unsigned)min(16 * b + 4 * g + r, Np - 1) * (kTile * 4);
+#pragma unroll
+          for (int fl = 0; fl < 4; ++fl) rv[b][r][fl] = fldn(Rr, o, fl * FS);
+        }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (f == 3) {
+      // the last reads of the copy (face 3's own traces, the update's q),
+      // then the next tile's direct loads
+#pragma unroll
+      for (int jj = 0; jj < FK; ++jj) {
+        const int n = smask[3 * Nfp + min(4 * jj + g, Nfp - 1)];
+#pragma unroll
+        for (int fl = 0; fl < 4; ++fl) own3[jj][fl] = bq[(fl * Np + n) * kTile];
+      }
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int n = min(16 * b + 4 * g + r, Np - 1);
+#pragma unroll
+          for (int fl = 0; fl < 4; ++fl) qd[b][r][fl] = bq[(fl * Np + n) * kTile];
+        }
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): every LDS read returned
+      __builtin_amdgcn_sched_barrier(0);
+      if (next >= 0) tile_dma_f<N>(L, qo, sh, next, ngrp, buf, lane);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const FaceInF<N>& x = fb[f];
+    const float cr = f == 2 ? 1.f : (f == 3 ? -1.f : 0.f);
+    const float cs = f == 2 ? 1.f : (f == 1 ? -1.f : 0.f);
+    const float ct = f == 2 ? 1.f : (f == 0 ? -1.f : 0.f);
+    float nx = cr * rx + cs * sx + ct * tx;
+    float ny = cr * ry + cs * sy + ct * ty;
+    float nz = cr * rz + cs * sz + ct * tz;
+    const float fsc = sqrtf(nx * nx + ny * ny + nz * nz);
+    const float inv = 1.f / fsc;
+    nx *= inv;
+    ny *= inv;
+    nz *= inv;
+    const int code = fcode[f];
+    const float ZP = fz[f];
+    const bool inner = code >= 0;
+    const int cb = -1 - code;
+    const bool hb = !inner && (cb & 3) == 0;
+    const bool dir = !inner && (cb & 3) == 2;
+    const float iZ = 1.f / (Z + ZP);
+    const float aM = ZP * iZ, aP = Z * iZ, bZ = Z * aM;
+    const float cP = fsc * Kb;
+#pragma unroll
+    for (int jj = 0; jj < FK; ++jj) {
+      float pM, uM, vM, wM;
+      if (f == 3) {
+        pM = own3[jj][0];
+        uM = own3[jj][1];
+        vM = own3[jj][2];
+        wM = own3[jj][3];
+      } else {
+        const int n = smask[f * Nfp + min(4 * jj + g, Nfp - 1)];
+        pM = bq[n * kTile];
+        uM = bq[(Np + n) * kTile];
+        vM = bq[(2 * Np + n) * kTile];
+        wM = bq[(3 * Np + n) * kTile];
+      }
+      const float pP = x.p[jj], uP = x.u[jj], vP = x.v[jj], wP = x.w[jj];
+      const float unM = nx * uM + ny * vM + nz * wM;
+      const float unP = nx * uP + ny * vP + nz * wP;
+      const float pG = inner ? pP : (dir ? -pM : (hb ? 2.f * x.rb[jj] : 0.f));
+      const float uG = inner ? unP : (dir ? unM : 0.f);
+      const float pF = aM * pM + aP * pG + bZ * (unM - uG);
+      const float unF = iZ * (pM - pG) + aP * unM + aM * uG;
+      const float fp = cP * (unM - unF);
+      const float fu = pM - pF;
+      const float* fl = fragL + (f * FK + jj) * 64;
+      if (f == 2) {
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          const float a = fl[b * 4 * FK * 64];
+          rp[b] = mfma16(a, fp, rp[b]);
+          dpr[b] = mfma16(a, -fu, dpr[b]);
+          dps[b] = mfma16(a, -fu, dps[b]);
+          dpt[b] = mfma16(a, -fu, dpt[b]);
+        }
+      } else {
+        f4* G = f == 0 ? dpt : (f == 1 ? dps : dpr);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          const float a = fl[b * 4 * FK * 64];
+          rp[b] = mfma16(a, fp, rp[b]);
+          G[b] = mfma16(a, fu, G[b]);
+        }
+      }
+    }
+  }
+
+  // point source on its element (a uniform branch only that wave takes)
+  {
+    const double* sp = sh.srcp + 4 * shot;
+    const bool src = (double)e == sp[0];
+    if (__builtin_amdgcn_read_exec() & __ballot(src)) {
+      const double trr = stage_time(sh) - sp[2], arr = M_PI * sp[1] * trr;
+      const float src_s = (float)(sp[3] * trr * exp(-arr * arr));
+      const double* src_w = sh.srcw + (size_t)shot * Np;
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (src) rp[b][r] += (float)src_w[min(16 * b + 4 * g + r, Np - 1)] * src_s;
+    }
+  }
+
+  // ---- LSRK update: 32 RB stores, every lane issuing them (a lane without
+  // a row stores past the end of the resource, which the hardware drops)
+  __builtin_amdgcn_sched_barrier(0);
+  const bool live = irho != 0.f;
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = 16 * b + 4 * g + r;
+      const unsigned o = (live && n < Np) ? tb + (unsigned)n * (kTile * 4) : 0xFFFFFFF8u;
+      const float a = dpr[b][r], bq_ = dps[b][r], c = dpt[b][r];
+      const float rhs[4] = {rp[b][r],
+                            -irho * (rx * a + sx * bq_ + tx * c),
+                            -irho * (ry * a + sy * bq_ + ty * c),
+                            -irho * (rz * a + sz * bq_ + tz * c)};
+#pragma unroll
+      for (int fl = 0; fl < 4; ++fl) {
+        const float rr = A * rv[b][r][fl] + dt * rhs[fl];
+        fstn(Rr, o, fl * FS, rr);
+        fstn(Rn, o, fl * FS, qd[b][r][fl] + B * rr);
+      }
+    }
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kWavesF * 64, 1) k_level3_f32_dma(
+    Lvl3 L, const float* __restrict__ qo, float* __restrict__ qn, float* __restrict__ res,
+    const double* __restrict__ qb3, float A, float B, float dt, Shots sh) {
+  using D = Dims3f<N>;
+  constexpr int Nfp = D::Nfp;
+  extern __shared__ float sfl[];
+  int* smask = reinterpret_cast<int*>(sfl);
+  int* smap = smask + 4 * Nfp;
+  float* sops = sfl + 4 * Nfp + 96 * Nfp;
+  const int lane = threadIdx.x & 63;
+  const int ngrp = (L.ntile + kWavesF - 1) / kWavesF;
+  const XcdRange rg_(ngrp * (long long)sh.n, L.order);
+  char* buf = reinterpret_cast<char*>(sops + D::NOPS) +
+              __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * BufF<N>::BYTES;
+  if (rg_.lo < rg_.hi) tile_dma_f<N>(L, qo, sh, rg_.lo, ngrp, buf, lane);
+  fill_lds<kWavesF * 64, 4 * Nfp>(smask, L.fmask, threadIdx.x);
+  fill_lds<kWavesF * 64, 96 * Nfp>(smap, L.fmap, threadIdx.x);
+  fill_lds<kWavesF * 64, D::NOPS>(sops, L.ops32, threadIdx.x);
+  __syncthreads();
+  for (long long it = rg_.lo; it < rg_.hi; it += rg_.step) {
+    const long long nx = it + rg_.step;
+    tile_f32_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, it, nx < rg_.hi ? nx : -1, ngrp, smap,
+                    smask, sops, buf, lane);
+  }
+}
+
+template <int N>
+hipError_t launch3f_dma(const Lvl3& L, const float* qo, float* qn, float* res, const double* qb3,
+                        double A, double B, double dt, const Shots& sh, hipStream_t st) {
+  using D = Dims3f<N>;
+  constexpr int Nfp = D::Nfp;
+  const size_t lds = sizeof(float) * (4 * Nfp + 96 * Nfp + D::NOPS) +
+                     (size_t)kWavesF * BufF<N>::BYTES;
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_level3_f32_dma<N>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  if (sh.n < 1) return hipErrorInvalidValue;
+  const int ngrp = (L.ntile + kWavesF - 1) / kWavesF;
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3_f32_dma<N>, kWavesF * 64,
+                                                       lds);
+    if (e != hipSuccess) return e;
+    resident = std::max(1, per_cu) * prop.multiProcessorCount;
+  }
+  const long long items = (long long)ngrp * sh.n;
+  const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, items) / 8 * 8);
+  hipLaunchKernelGGL(k_level3_f32_dma<N>, dim3(blocks), dim3(kWavesF * 64), lds, st, L, qo, qn,
+                     res, qb3, (float)A, (float)B, (float)dt, sh);
+  return hipGetLastError();
+}
+
 template <int N>
 hipError_t launch3f(const Lvl3& L, const float* qo, float* qn, float* res, const double* qb3,
                     double A, double B, double dt, const Shots& sh, hipStream_t st) {
+  if constexpr (N <= 4) {
+    if (L.kvar == 0) return launch3f_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+  }
   using D = Dims3f<N>;
   constexpr int Nfp = D::Nfp;
   const size_t lds = sizeof(float) * (4 * Nfp + 96 * Nfp + (D::kLds ? D::NOPS : 0));
