@@ -42,7 +42,10 @@ struct Dims3 {
   static constexpr int RG = (Np + 3) / 4;     // row groups (also volume k-steps)
   static constexpr int FK = (Nfp + 3) / 4;    // lifting k-steps per face
   static constexpr int NFRAG = 3 * RG * RG + RG * 4 * FK;   // 16 doubles each
-  static constexpr bool kLds = NFRAG * 16 * 8 <= 64 * 1024;
+  // operator fragments in LDS up to 150 KB (N <= 6); above 64 KB the kernel
+  // runs one workgroup per CU, with 512 registers per wave
+  static constexpr bool kLds = NFRAG * 16 * 8 <= 150 * 1024;
+  static constexpr int kOcc = NFRAG * 16 * 8 <= 64 * 1024 ? 2 : 1;
 };
 
 // Buffer-resource access: a 32-bit per-lane byte offset plus a uniform
@@ -77,7 +80,7 @@ __device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restric
                                           int lane);
 
 template <int N>
-__global__ void __launch_bounds__(kWaves3 * 64, 2) k_level3(Lvl3 L, const double* __restrict__ qo,
+__global__ void __launch_bounds__(kWaves3 * 64, Dims3<N>::kOcc) k_level3(Lvl3 L, const double* __restrict__ qo,
                                                    double* __restrict__ qn, double* __restrict__ res,
                                                    const double* __restrict__ qb3, double A, double B,
                                                    double dt, Shots sh) {
