@@ -135,3 +135,26 @@ def test_trained_closure_beats_basic_abc():
     print(f"[closure] energy over 3000 steps: {e_start:.3e} -> "
           f"{', '.join(f'{e:.2e}' for e in energies)}", flush=True)
     assert all(b <= a * (1 + 1e-9) for a, b in zip([e_start] + energies, energies))
+
+
+def test_bad_closure_weights_cannot_add_energy():
+    """Deliberately bad (large random) weights: the reflection gain stays
+    within g_max <= 1, so the energy never grows and no value blows up."""
+    from paper_1610_05023_amd import Solver
+    from paper_1610_05023_amd.closure import gaussian_state
+    n, N = 6, 3
+    VX, E = w.kuhn_mesh(n)
+    K = E.shape[0]
+    rng = np.random.default_rng(13)
+    wts = (5.0 * rng.standard_normal(NPARAM)).astype(np.float32)
+    wts[0], wts[1] = 3.0, 1.0
+    s = Solver(VX, E, N, 0, np.ones(K), np.ones(K)).bind()
+    s.set_state(gaussian_state(s, (0.35, 0.6, 0.45), 0.15))
+    s.set_closure(wts)
+    prev = s.energy()
+    for _ in range(8):
+        s.step(100, w.kuhn_dt(n, N, 1.0))
+        st, e = s.check(e_ref=prev, rel_tol=1e-9)
+        assert st == "DGH_OK", (st, e, prev)
+        prev = e
+    print(f"[closure] bad weights: energy after 800 steps {prev:.3e}", flush=True)
