@@ -144,6 +144,9 @@ def main():
     ap.add_argument("--habc", type=int, default=None, help="override the HABC order P")
     ap.add_argument("--autotune", action="store_true",
                     help="time the 3D launch candidates on this workload and keep the fastest")
+    ap.add_argument("--closure", action="store_true",
+                    help="P = 0 with the learned boundary closure (seeded random weights: the "
+                         "cost does not depend on them)")
     ap.add_argument("--graph", action="store_true",
                     help="replayed stepping: every step runs as one captured HIP graph")
     ap.add_argument("--calib-copy", action="store_true",
@@ -180,6 +183,8 @@ def main():
         wl["dt"] = __import__("workloads").kuhn_dt(wl["n"], wl["N"], float(wl["c"].max()))
     if args.habc is not None:
         wl["P"] = args.habc
+    if args.closure:
+        wl["P"] = 0
     K = wl["E"].shape[0]
     t_setup = time.perf_counter()
     prec = 2 if args.precision == "fp32" else 0
@@ -195,6 +200,11 @@ def main():
     print(f"[bench] setup {time.perf_counter() - t_setup:.1f} s; K={K} Ktri={k['Ktri']} "
           f"Klin={k['Klin']} unknowns={U}", file=sys.stderr, flush=True)
     dt = wl["dt"]
+    if args.closure:
+        from paper_1610_05023_amd.binding import CLOSURE_PARAMS
+        wts = (0.1 * np.random.default_rng(5).standard_normal(CLOSURE_PARAMS)).astype(np.float32)
+        wts[0], wts[1] = 1.0, 0.95
+        s.set_closure(wts)
     tuned = None
     if args.autotune:
         best, ms = s.autotune(10)
@@ -265,6 +275,7 @@ def main():
                    "N": wl["N"], "P": wl["P"], "unknowns": U, "dt": dt,
                    "parallelism": "single GPU",
                    "step_mode": "hip graph per step" if args.graph else "eager launches",
+                   "boundary": "learned closure (P = 0)" if args.closure else f"HABC P={wl['P']}",
                    "tuning": tuned if tuned is not None else "default (tile on chip, XCD ranges)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -158,3 +158,29 @@ def test_bad_closure_weights_cannot_add_energy():
         assert st == "DGH_OK", (st, e, prev)
         prev = e
     print(f"[closure] bad weights: energy after 800 steps {prev:.3e}", flush=True)
+
+
+def test_closure_in_the_step_matches_reference_network():
+    """The r- the step's closure kernel writes (qb3) equals the FP64
+    reference network on the inputs of that step end (sampled with
+    closure_sample), for a random network on a propagating pulse."""
+    from paper_1610_05023_amd import Solver
+    from paper_1610_05023_amd.closure import gaussian_state
+    n, N = 6, 3
+    VX, E = w.kuhn_mesh(n)
+    K = E.shape[0]
+    wts = init_params(21, in_scale=1.3, g_max=0.9)
+    wts[2:] += 0.05 * np.random.default_rng(22).standard_normal(NPARAM - 2)
+    wts = wts.astype(np.float32)
+    s = Solver(VX, E, N, 0, np.ones(K), np.ones(K)).bind()
+    s.set_state(gaussian_state(s, (0.4, 0.55, 0.5), 0.15))
+    s.set_closure(wts)
+    s.step(120, w.kuhn_dt(n, N, 1.0))
+    X, _ = s.closure_sample()
+    qb3 = s.read_fields(["qb3"])["qb3"].ravel()
+    ref, _ = forward(wts.astype(np.float64), X.astype(np.float64))
+    scale = np.max(np.abs(X[:, 10]))
+    err = np.max(np.abs(qb3 - ref)) / scale
+    print(f"[closure] step r- vs reference network: max |diff| / max |r+| = {err:.1e} "
+          f"({len(ref)} nodes, max |r-| / max |r+| = {np.max(np.abs(ref)) / scale:.2f})", flush=True)
+    assert err < 2e-5
