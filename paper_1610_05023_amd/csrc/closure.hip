@@ -24,6 +24,8 @@
 // holds the 10 raw inputs and r+ (11 floats).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "levels.hpp"
 
@@ -255,16 +257,61 @@ __device__ __forceinline__ void node_trace(const Lvl2& L2, const T3* __restrict_
 // absorbing-face node comes from the current traces and the 4 step ends
 // before them -> qb3, which every stage of the next step reads; q0_3 =
 // r+ + r- (kept for symmetry with the face rule).  The inputs are those
-// k_closure_sample records after a step of the plain method.  One thread
-// per node.
+// k_closure_sample records after a step of the plain method.
+//
+// The network runs on the FP32 16x16x4 MFMA, 16 nodes per wave: a layer is
+// H_out[64][16] = W[64][K] H_in[K][16] with the weights as A fragments (lane
+// l: W[16 rb + l%16][4 ks + l/16], arranged in LDS in that order, in_scale
+// folded into W1) and the activations as B fragments (lane l: H_in[4 ks +
+// l/16][node l%16]).  The accumulator rows a lane holds (16 rb + 4 (l/16) +
+// r) are not the B rows of the next layer, so each hidden layer goes
+// through a per-wave LDS tile [64][16] between layers.  The output row W4
+// is a dot product: partial sums over a lane's 16 rows, then across the 4
+// lane groups of a node.
+typedef float cf4 __attribute__((ext_vector_type(4)));
+constexpr int kCW = 4;                       // waves per workgroup
+constexpr int kA1 = 4 * 3 * 64;              // W1 fragments (K = 10 padded to 12)
+constexpr int kA2 = 4 * 16 * 64;             // W2 (and W3) fragments
+constexpr int kCF = kA1 + 2 * kA2 + 4 * kH + 2;   // + b1, b2, b3, W4, b4, g_max
+
+__device__ __forceinline__ cf4 mfma_c(float a, float b, cf4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 template <class T3>
-__global__ void __launch_bounds__(kThreads) k_closure(Lvl2 L2, const float* __restrict__ W,
+__global__ void __launch_bounds__(kCW * 64) k_closure(Lvl2 L2, const float* __restrict__ W,
                                                       const T3* __restrict__ q3, int np3,
                                                       float* __restrict__ hist,
                                                       double* __restrict__ qb3,
                                                       double* __restrict__ q03, Shots sh) {
-  __shared__ float w[kNW];
-  for (int i = threadIdx.x; i < kNW; i += blockDim.x) w[i] = W[i];
+  __shared__ float cw[kCF];
+  __shared__ float tl[kCW][kH * 16];        // per wave: a hidden layer, [row][node]
+  // weights in fragment order
+  for (int i = threadIdx.x; i < kA1; i += blockDim.x) {
+    const int rb = i / 192, ks = (i / 64) % 3, l = i & 63;
+    const int row = 16 * rb + (l & 15), col = 4 * ks + (l >> 4);
+    cw[i] = col < kIn ? W[0] * W[oW1 + row * kIn + col] : 0.f;
+  }
+  for (int i = threadIdx.x; i < kA2; i += blockDim.x) {
+    const int rb = i / 1024, ks = (i / 64) % 16, l = i & 63;
+    const int rc = (16 * rb + (l & 15)) * kH + 4 * ks + (l >> 4);
+    cw[kA1 + i] = W[oW2 + rc];
+    cw[kA1 + kA2 + i] = W[oW3 + rc];
+  }
+  float* cb1 = cw + kA1 + 2 * kA2;
+  float* cb2 = cb1 + kH;
+  float* cb3 = cb2 + kH;
+  float* cw4 = cb3 + kH;
+  for (int i = threadIdx.x; i < kH; i += blockDim.x) {
+    cb1[i] = W[ob1 + i];
+    cb2[i] = W[ob2 + i];
+    cb3[i] = W[ob3 + i];
+    cw4[i] = W[oW4 + i];
+  }
+  if (threadIdx.x == 0) {
+    cw4[kH] = W[ob4];
+    cw4[kH + 1] = W[1];
+  }
   __syncthreads();
   const size_t k = blockIdx.y;
   q3 += k * sh.st3;
@@ -272,21 +319,82 @@ __global__ void __launch_bounds__(kThreads) k_closure(Lvl2 L2, const float* __re
   q03 += k * sh.stb3;
   const int nn = L2.Kt * L2.Np;
   hist += k * (size_t)nn * kHist;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= nn) return;
-  const int t = x / L2.Np, a = x - t * L2.Np;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane >> 4, nd = lane & 15;
+  // persistent: the workgroup staged the weights once; its waves walk the
+  // 16-node tiles
+  for (int x0 = (blockIdx.x * kCW + wv) * 16; x0 < nn; x0 += gridDim.x * kCW * 16) {
+  const int x = x0 + nd;                     // this lane's node
+  const bool valid = x < nn;
+  const int xc = valid ? x : nn - 1;
+  const int t = xc / L2.Np, a = xc - t * L2.Np;
   float f[kHist], zun;
   node_trace(L2, q3, np3, t, a, f[0], zun, f[1]);
 #pragma unroll
-  for (int j = 0; j < kHist - 2; ++j) f[2 + j] = hist[(size_t)x * kHist + j];
-  float* o = hist + (size_t)x * kHist;
+  for (int j = 0; j < kHist - 2; ++j) f[2 + j] = hist[(size_t)xc * kHist + j];
+  if (valid && q == 0) {
+    float* o = hist + (size_t)x * kHist;
 #pragma unroll
-  for (int j = 0; j < kHist; ++j) o[j] = f[j];
-  const float rpf = 0.5f * (f[0] + zun);
-  const float th = tanhf(mlp_eval(w, f, input_inv_rms(f), nullptr, 0));
-  const double rm = (double)(w[1] * th * rpf);
-  qb3[x] = rm;
-  q03[x] = (double)rpf + rm;
+    for (int j = 0; j < kHist; ++j) o[j] = f[j];
+  }
+  const float inv = input_inv_rms(f);
+  float* T = tl[wv];
+  const float* A1 = cw + lane;
+  const float* A2 = cw + kA1 + lane;
+  const float* A3 = cw + kA1 + kA2 + lane;
+  // layer 1: B = the lane group's inputs (feature 4 ks + q of node nd)
+  cf4 acc[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) acc[rb] = cf4{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < 3; ++ks) {
+    const int c0 = 4 * ks;
+    float v = q == 0 ? f[c0] : (q == 1 ? f[c0 + 1] : 0.f);
+    if (c0 + 2 < kIn && q == 2) v = f[c0 + 2];
+    if (c0 + 3 < kIn && q == 3) v = f[c0 + 3];
+    v *= inv;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[rb] = mfma_c(A1[(rb * 3 + ks) * 64], v, acc[rb]);
+  }
+  // hidden layers 2 and 3 through the LDS tile
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+    const float* bias = layer == 0 ? cb1 : cb2;
+    const float* A = layer == 0 ? A2 : A3;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * rb + 4 * q + r;
+        T[row * 16 + nd] = tanhf(acc[rb][r] + bias[row]);
+      }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[rb] = cf4{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const float v = T[(4 * ks + q) * 16 + nd];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) acc[rb] = mfma_c(A[(rb * 16 + ks) * 64], v, acc[rb]);
+    }
+  }
+  // output: y = W4 . tanh(acc + b3) + b4, summed over the node's 4 lane groups
+  float y = 0.f;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rb + 4 * q + r;
+      y += cw4[row] * tanhf(acc[rb][r] + cb3[row]);
+    }
+  y += __shfl_xor(y, 16, 64);
+  y += __shfl_xor(y, 32, 64);
+  y += cw4[kH];
+  if (valid && q == 0) {
+    const float rpf = 0.5f * (f[0] + zun);
+    const double rm = (double)(cw4[kH + 1] * tanhf(y) * rpf);
+    qb3[x] = rm;
+    q03[x] = (double)rpf + rm;
+  }
+  }
 }
 
 // End of a step: the history (5 step ends, most recent first) moves one
@@ -385,7 +493,19 @@ hipError_t launch_closure(const Lvl2& L2, const float* W, const void* q3, int q3
                           hipStream_t st) {
   const int nn = L2.Kt * L2.Np;
   if (nn == 0) return hipSuccess;
-  const dim3 g((nn + kThreads - 1) / kThreads, sh.n), b(kThreads);
+  const int tiles = (nn + 15) / 16;
+  // persistent over the tiles of each shot: about 3 workgroups per CU in all
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return e;
+    cus = prop.multiProcessorCount;
+  }
+  const int per_shot = std::max(1, 3 * cus / std::max(1, sh.n));
+  const dim3 g(std::min((tiles + kCW - 1) / kCW, per_shot), sh.n), b(kCW * 64);
   if (q3f32)
     hipLaunchKernelGGL(k_closure<float>, g, b, 0, st, L2, W, static_cast<const float*>(q3), np3,
                        hist, qb3, q03, sh);
