@@ -715,33 +715,42 @@ __global__ void __launch_bounds__(kWavesR * 64, 1) k_level3_dma(Lvl3 L, const do
 // One block per tile; partial sum of J/2 (p M p / (rho c^2) + rho u M u),
 // accumulated in FP64 whatever the state's type.
 template <class T>
-__global__ void k_energy(Lvl3 L, const T* __restrict__ q, const double* __restrict__ mass,
-                         const double* __restrict__ J, double* __restrict__ out) {
-  const int Np = L.Np, tile = blockIdx.x, tid = threadIdx.x, es = tid & 15, g = tid >> 4;
-  const int e = tile * kTile + es;
-  __shared__ double red[256];
-  double acc = 0.0;
+__global__ void __launch_bounds__(256) k_energy(Lvl3 L, const T* __restrict__ q,
+                                                const double* __restrict__ mass,
+                                                const double* __restrict__ J,
+                                                double* __restrict__ out) {
+  // the mass matrix and the tile's four fields in LDS (sized at launch)
+  extern __shared__ double sm[];
+  const int Np = L.Np, tile = blockIdx.x, tid = threadIdx.x;
+  double* sq = sm + Np * Np;
+  for (int i = tid; i < Np * Np; i += 256) sm[i] = mass[i];
+  const T* qt = q + (size_t)tile * 4 * Np * kTile;
+  for (int i = tid; i < 4 * Np * kTile; i += 256) sq[i] = (double)qt[i];
+  __syncthreads();
+  const int es = tid & 15, g = tid >> 4;
   const double* gt = L.geo + (size_t)tile * 12 * kTile + es;
   const double irho = gt[9 * kTile], Kb = gt[10 * kTile];
+  double acc = 0.0;
   if (irho != 0.0) {
-    const T* qt = q + (size_t)tile * 4 * Np * kTile + es;
     const double rho = 1.0 / irho;
     for (int a = g; a < Np; a += 16) {
       double mq[4] = {0, 0, 0, 0};
       for (int b = 0; b < Np; ++b) {
-        const double m = mass[a * Np + b];
-        for (int f = 0; f < 4; ++f) mq[f] += m * (double)qt[(f * Np + b) * kTile];
+        const double m = sm[a * Np + b];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) mq[f] += m * sq[(f * Np + b) * kTile + es];
       }
-      acc += (double)qt[a * kTile] * mq[0] / Kb +
-             rho * ((double)qt[(Np + a) * kTile] * mq[1] + (double)qt[(2 * Np + a) * kTile] * mq[2] +
-                    (double)qt[(3 * Np + a) * kTile] * mq[3]);
+      acc += sq[a * kTile + es] * mq[0] / Kb +
+             rho * (sq[(Np + a) * kTile + es] * mq[1] + sq[(2 * Np + a) * kTile + es] * mq[2] +
+                    sq[(3 * Np + a) * kTile + es] * mq[3]);
     }
-    acc *= 0.5 * J[e];
+    acc *= 0.5 * J[tile * kTile + es];
   }
+  double* red = sq + 4 * Np * kTile;
   red[tid] = acc;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) red[tid] += red[tid + st];
     __syncthreads();
   }
   if (tid == 0) out[tile] = red[0];
@@ -848,11 +857,22 @@ hipError_t launch_level3(const Lvl3& L, const double* qo, double* qn, double* re
 
 hipError_t launch_energy(const Lvl3& L, const void* q, int q_f32, const double* mass,
                          const double* J, double* out, hipStream_t st) {
+  const size_t lds = sizeof(double) * ((size_t)L.Np * L.Np + 4 * L.Np * kTile + 256);
+  static bool attr = false;   // N = 6 needs more than the default 64 KB
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_energy<float>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_energy<double>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
   if (q_f32)
-    hipLaunchKernelGGL(k_energy<float>, dim3(L.ntile), dim3(256), 0, st, L,
+    hipLaunchKernelGGL(k_energy<float>, dim3(L.ntile), dim3(256), lds, st, L,
                        static_cast<const float*>(q), mass, J, out);
   else
-    hipLaunchKernelGGL(k_energy<double>, dim3(L.ntile), dim3(256), 0, st, L,
+    hipLaunchKernelGGL(k_energy<double>, dim3(L.ntile), dim3(256), lds, st, L,
                        static_cast<const double*>(q), mass, J, out);
   return hipGetLastError();
 }
