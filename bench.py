@@ -93,6 +93,58 @@ def build_batch_workload(n=20, N=4, P=3, shots=64):
                 f0=2.0, t0=0.625, dt=w.kuhn_dt(n, N, 1.0), n=n, N=N, P=P, shots=shots)
 
 
+def run_uneven(args):
+    """Uneven batch: meshes of 10^3, 16^3 and 24^3 cells (x 6 tets), N = 4,
+    HABC P = 3, rho = c = 1, one Ricker source each at a seeded interior
+    position, FP64; stepped as one group (one 3D launch per stage over all
+    their tiles) and, for comparison, one after the other."""
+    import numpy as np
+    import torch
+    import workloads as w
+    from paper_1610_05023_amd import Solver
+    from paper_1610_05023_amd.binding import step_group
+    N, P, sizes = 4, 3, (10, 16, 24)
+    solvers, U = [], 0
+    xs = w.shot_positions(len(sizes), seed=6)
+    for j, n in enumerate(sizes):
+        VX, E = w.kuhn_mesh(n)
+        K = E.shape[0]
+        s = Solver(VX, E, N, P, np.ones(K), np.ones(K)).bind()
+        s.set_source(xs[j], 2.0, 0.625)
+        k = s.counts
+        U += w.n_unknowns(k["K"], k["Ktri"], k["Klin"], N, P)
+        solvers.append(s)
+    dt = w.kuhn_dt(max(sizes), N, 1.0)
+    step_group(solvers, args.warmup, dt, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_group(solvers, args.steps, dt, args.warmup * dt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(args.steps, dt, (args.warmup + args.steps) * dt)
+    torch.cuda.synchronize()
+    el_sep = time.perf_counter() - t0
+    finite = all(s.check()[0] == "DGH_OK" for s in solvers)
+    print(f"[bench] uneven group: {args.steps} steps in {el:.3f} s; one after the other "
+          f"{el_sep:.3f} s; check={finite}", file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC, "value": U * 5 * args.steps / el, "unit": "DOF-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "uneven group: FP64 DG+HABC steps of three Kuhn meshes of "
+                               "10^3, 16^3 and 24^3 cells x 6 tets stepped together, N=4, HABC "
+                               "P=3, rho=c=1, one Ricker source each (seed 6)",
+                   "unknowns": U, "dt": dt, "parallelism": "single GPU",
+                   "separate_ms_per_step": el_sep / args.steps * 1e3,
+                   "group_speedup": el_sep / el},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def cpu_baseline(seconds_target=20.0):
     """The FP64 oracle (numpy, as is) on a bounded sample of the workload:
     the same medium recipe, degree and HABC order on a 20^3 x 6 = 48,000-tet
@@ -134,7 +186,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=40)
-    ap.add_argument("--workload", choices=["layered", "batch"], default="layered",
+    ap.add_argument("--workload", choices=["layered", "batch", "uneven"], default="layered",
                     help="layered: the 40^3 layered-medium step (default); batch: 64 shots "
                          "on a 20^3 mesh stepped together")
     ap.add_argument("--shots", type=int, default=64)
@@ -171,6 +223,9 @@ def main():
         torch.cuda.synchronize()
         print("[bench] calibration: 1 GiB fill, 2 x (1 GiB read + 1 GiB write)", file=sys.stderr)
         del x, y
+    if args.workload == "uneven":
+        run_uneven(args)
+        return
     batch = args.workload == "batch"
     if batch:
         wl = build_batch_workload(shots=args.shots)

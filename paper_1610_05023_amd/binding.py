@@ -41,6 +41,7 @@ _SIGS = {
     "dgh_set_source": [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_double, C.c_double],
     "dgh_step": [C.c_void_p, C.c_int, C.c_double, C.c_double],
     "dgh_set_graph": [C.c_void_p, C.c_int],
+    "dgh_step_group": [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_double],
     "dgh_tuning_count": [C.c_void_p, C.POINTER(C.c_int)],
     "dgh_set_tuning": [C.c_void_p, C.c_int],
     "dgh_autotune": [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.c_void_p],
@@ -281,6 +282,17 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def step_group(solvers, n_steps, dt, t_start=0.0):
+    """Steps several bound Solvers (any mesh sizes, same N) together: one 3D
+    launch per stage over all of their tiles."""
+    arr = (C.c_void_p * len(solvers))(*[sv.h.value for sv in solvers])
+    st = load().dgh_step_group(C.cast(arr, C.c_void_p), len(solvers), int(n_steps), float(dt),
+                               float(t_start))
+    if st != DGH_OK:
+        msg = load().dgh_last_error(solvers[0].h).decode()
+        raise DghError(f"dgh_step_group: {STATUS.get(st, st)}: {msg}")
 
 
 # ---- training kernels of the closure (device tensors; no context)

@@ -40,6 +40,7 @@ struct Layout {
   Region qb1, info0, nrm0, T, srcw, srcp, wlines, wcorners, flags, ops2f;
   Region mlpw, hist, csamp;   // learned closure: parameters, trace history, samples
   Region clk;                 // device clock of replayed stepping {t0, steps}
+  Region grp;                 // member tables of a group step (two parities)
   // per-shot strides (doubles) of the state arrays
   size_t st3 = 0, st2 = 0, stb3 = 0, st1 = 0, stb2 = 0, stb1 = 0;
   size_t e3 = 8;   // bytes per element of the 3D state (8 FP64, 4 FP32)
@@ -489,6 +490,7 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.hist, S * nnode * 10 * sizeof(float));
   L.add(L.csamp, nnode * 12 * sizeof(float));   // rows of 11, then targets
   L.add(L.clk, 2 * sizeof(double));
+  L.add(L.grp, 2 * dgh::kMaxGroup * sizeof(dgh::Member3));
 }
 
 template <class V>
@@ -1140,6 +1142,85 @@ dgh_status dgh_autotune(dgh_ctx* c, int launches, int* best, double* ms) {
   c->L3.order = ibest & 1;
   drop_graphs(c);
   *best = ibest;
+  return DGH_OK;
+}
+
+dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, double t_start) {
+  if (!ctxs || n < 1 || n > dgh::kMaxGroup) return DGH_EINVAL;
+  dgh_ctx* c0 = ctxs[0];
+  if (!c0) return DGH_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    dgh_ctx* c = ctxs[i];
+    if (!c) return DGH_EINVAL;
+    if (c->stage < S_BOUND) return fail(c0, DGH_ESTATE, "group member not bound");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return fail(c0, DGH_EINVAL, "a context appears twice in the group");
+    if (c->lay.e3 != 8 || c->N > 4 || c->L3.kvar != 0)
+      return fail(c0, DGH_EINVAL, "group steps need FP64, N <= 4 and the tile-on-chip kernel");
+    if (c->N != c0->N || c->device != c0->device || c->stream != c0->stream)
+      return fail(c0, DGH_EINVAL, "group members need the same N, device and stream");
+    if (c->closure || c->record) return fail(c0, DGH_EINVAL, "group steps run the plain method");
+  }
+  if (n_steps < 0 || !(dt > 0) || !std::isfinite(t_start)) return fail(c0, DGH_EINVAL, "bad step arguments");
+  if (n_steps == 0) return DGH_OK;
+  hipStream_t st = c0->stream;
+  // member tables for both parities of the double buffers; the previous
+  // group step may still read them, so the stream drains first
+  std::vector<dgh::Member3> hd(2 * n);
+  long long first = 0;
+  for (int i = 0; i < n; ++i) {
+    dgh_ctx* c = ctxs[i];
+    const Layout& L = c->lay;
+    const int ngrp = (c->ntile + 3) / 4;
+    for (int p = 0; p < 2; ++p) {
+      const int o = c->cur ^ p;
+      dgh::Member3& m = hd[p * n + i];
+      m.L = c->L3;
+      m.qo = c->ws + L.q3[o].off;
+      m.qn = c->ws + L.q3[1 - o].off;
+      m.res = c->ws + L.res3.off;
+      m.qb3 = dptr<double>(c, L.qb3);
+      m.sh = dgh::Shots{c->n_shots, L.st3, L.st2, L.stb3, L.st1, L.stb2, L.stb1,
+                        dptr<double>(c, L.srcw), dptr<double>(c, L.srcp), 0.0, nullptr, 0.0, dt};
+      m.first = first;
+      m.ngrp = ngrp;
+    }
+    first += (long long)ngrp * c->n_shots;
+  }
+  const long long total = first;
+  dgh::Member3* dev = dptr<dgh::Member3>(c0, c0->lay.grp);
+  HIPCHECK(c0, hipStreamSynchronize(st));
+  HIPCHECK(c0, hipMemcpy(dev, hd.data(), hd.size() * sizeof(dgh::Member3), hipMemcpyHostToDevice));
+  for (int it = 0; it < n_steps; ++it) {
+    const double t = t_start + it * dt;
+    for (int s = 0; s < 5; ++s) {
+      const int par = (it * 5 + s) & 1;
+      HIPCHECK(c0, dgh::launch_level3_group(dev + par * n, n, total, c0->N, kA[s], kB[s], dt,
+                                            t + kC[s] * dt, kC[s], st));
+      for (int i = 0; i < n; ++i) {
+        dgh_ctx* c = ctxs[i];
+        const Layout& L = c->lay;
+        const int o = c->cur, nn = 1 - c->cur;
+        const dgh::Shots sh{c->n_shots, L.st3, L.st2, L.stb3, L.st1, L.stb2, L.stb1,
+                            dptr<double>(c, L.srcw), dptr<double>(c, L.srcp),
+                            t + kC[s] * dt, nullptr, kC[s], dt};
+        const dgh::FaceBufs fb{dptr<double>(c, L.q2[o]), dptr<double>(c, L.q2[nn]),
+                               dptr<double>(c, L.res2), dptr<double>(c, L.qb3),
+                               dptr<double>(c, L.q03), c->ws + L.q3[nn].off,
+                               dptr<double>(c, L.qb2), 0};
+        HIPCHECK(c0, dgh::launch_faces(c->LF, c->L2, fb, sh, kA[s], kB[s], dt, st));
+        HIPCHECK(c0, dgh::launch_boundary(c->LB, c->L2, c->L1, c->L0, c->L3,
+                                          dptr<double>(c, L.q2[o]), dptr<double>(c, L.q2[nn]),
+                                          dptr<double>(c, L.res2), dptr<double>(c, L.qb2),
+                                          dptr<double>(c, L.qb3), dptr<double>(c, L.q03),
+                                          dptr<double>(c, L.q3[nn]), dptr<double>(c, L.q1[o]),
+                                          dptr<double>(c, L.q1[nn]), dptr<double>(c, L.res1),
+                                          dptr<double>(c, L.qb1), dptr<double>(c, L.q02), kA[s],
+                                          kB[s], dt, sh, st));
+        c->cur = nn;
+      }
+    }
+  }
   return DGH_OK;
 }
 

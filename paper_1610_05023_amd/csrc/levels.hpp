@@ -119,6 +119,23 @@ struct Shots {
   double dt;
 };
 
+// One member of a group step (several contexts with the same N in one 3D
+// launch): its level, buffers and shots, and its range of the work list.
+struct Member3 {
+  Lvl3 L;
+  const void* qo;
+  void* qn;
+  void* res;
+  const double* qb3;
+  Shots sh;
+  long long first;   // first item of the group's work list owned by this member
+  int ngrp;          // tile groups per shot
+};
+constexpr int kMaxGroup = 8;
+// FP64, N <= 4 (the tile-on-chip kernel); G in device memory
+hipError_t launch_level3_group(const Member3* G, int nm, long long total, int N, double A,
+                               double B, double dt, double tau, double cs, hipStream_t st);
+
 // the device clock of replayed stepping: clk = {t0, 0}; clk[1] += 1
 hipError_t launch_clock_set(double* clk, double t0, hipStream_t st);
 hipError_t launch_clock_tick(double* clk, hipStream_t st);

@@ -439,14 +439,15 @@ __device__ __forceinline__ void face_fetch(FaceIn<N>& x, int f, int code, int e,
   }
 }
 
-// One work item whose tile is in buf; issues the loads of item `next` (if
-// >= 0) into buf once the tile's copy has been read.
-template <int N>
+// One work item whose tile is in buf; calls fetch_next() (which issues the
+// direct loads of the next item, if any, into buf) once the tile's copy has
+// been read.
+template <int N, class Fetch>
 __device__ __forceinline__ void tile_step_dma(const Lvl3& L, const double* __restrict__ qo,
                                               double* __restrict__ qn, double* __restrict__ res,
                                               const double* __restrict__ qb3, double A, double B,
                                               double dt, const Shots& sh, long long item,
-                                              long long next, int ngrp, const int* smap,
+                                              Fetch fetch_next, int ngrp, const int* smap,
                                               const int* smask, const double* sops, char* buf,
                                               int lane) {
   using D = Dims3<N>;
@@ -465,7 +466,7 @@ __device__ __forceinline__ void tile_step_dma(const Lvl3& L, const double* __res
   if (tile >= L.ntile) {
     // no stores follow: wait for the next tile's direct loads here
     __builtin_amdgcn_s_waitcnt(0);
-    if (next >= 0) tile_dma<N>(L, qo, sh, next, ngrp, buf, lane);
+    fetch_next();
     __builtin_amdgcn_s_waitcnt(0);
     return;
   }
@@ -571,7 +572,7 @@ __device__ __forceinline__ void tile_step_dma(const Lvl3& L, const double* __res
         }
       __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): every LDS read returned
       __builtin_amdgcn_sched_barrier(0);
-      if (next >= 0) tile_dma<N>(L, qo, sh, next, ngrp, buf, lane);
+      fetch_next();
       __builtin_amdgcn_sched_barrier(0);
     }
     const FaceIn<N>& x = fb[f];
@@ -706,8 +707,70 @@ __global__ void __launch_bounds__(kWavesR * 64, 1) k_level3_dma(Lvl3 L, const do
   __syncthreads();
   for (long long it = rg_.lo; it < rg_.hi; it += rg_.step) {
     const long long nx = it + rg_.step;
-    tile_step_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, it, nx < rg_.hi ? nx : -1, ngrp, smap,
-                     smask, sops, buf, lane);
+    auto fetch = [&]() {
+      if (nx < rg_.hi) tile_dma<N>(L, qo, sh, nx, ngrp, buf, lane);
+    };
+    tile_step_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, it, fetch, ngrp, smap, smask, sops, buf,
+                     lane);
+  }
+}
+
+// The same kernel over a group of contexts (meshes of any size, same N):
+// one work list, member c owning the items [first_c, first_c + items_c);
+// the tables and operators in LDS depend on N only.  The next item's direct
+// loads may come from another member.
+template <int N>
+__global__ void __launch_bounds__(kWavesR * 64, 1) k_level3_dma_group(
+    const Member3* __restrict__ G, int nm, long long total, double A, double B, double dt,
+    double tau, double cs) {
+  using D = Dims3<N>;
+  constexpr int Nfp = D::Nfp;
+  extern __shared__ double sfrag[];
+  int* smask = reinterpret_cast<int*>(sfrag);
+  int* smap = smask + 4 * Nfp;
+  constexpr int kTabDoubles = (4 * Nfp + 96 * Nfp + 1) / 2;
+  const int lane = threadIdx.x & 63;
+  const XcdRange rg_(total, G[0].L.order);
+  double* sops = sfrag + kTabDoubles;
+  char* buf = reinterpret_cast<char*>(sops + D::NFRAG * 16) +
+              __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * BufR<N>::BYTES;
+  auto member = [&](long long it) {
+    int c = 0;
+    while (c + 1 < nm && G[c + 1].first <= it) ++c;
+    return c;
+  };
+  auto shots = [&](int c) {
+    Shots sh = G[c].sh;
+    sh.tau = tau;
+    sh.cs = cs;
+    sh.clk = nullptr;
+    return sh;
+  };
+  if (rg_.lo < rg_.hi) {
+    const int c = member(rg_.lo);
+    const Shots sh = shots(c);
+    tile_dma<N>(G[c].L, static_cast<const double*>(G[c].qo), sh, rg_.lo - G[c].first, G[c].ngrp,
+                buf, lane);
+  }
+  fill_lds<kWavesR * 64, 4 * Nfp>(smask, G[0].L.fmask, threadIdx.x);
+  fill_lds<kWavesR * 64, 96 * Nfp>(smap, G[0].L.fmap, threadIdx.x);
+  fill_lds<kWavesR * 64, D::NFRAG * 16>(sops, G[0].L.ops, threadIdx.x);
+  __syncthreads();
+  for (long long it = rg_.lo; it < rg_.hi; it += rg_.step) {
+    const long long nx = it + rg_.step;
+    const int c = member(it);
+    const Shots sh = shots(c);
+    auto fetch = [&]() {
+      if (nx < rg_.hi) {
+        const int cn = member(nx);
+        const Shots shn = shots(cn);
+        tile_dma<N>(G[cn].L, static_cast<const double*>(G[cn].qo), shn, nx - G[cn].first,
+                    G[cn].ngrp, buf, lane);
+      }
+    };
+    tile_step_dma<N>(G[c].L, static_cast<const double*>(G[c].qo), static_cast<double*>(G[c].qn),
+                     static_cast<double*>(G[c].res), G[c].qb3, A, B, dt, sh, it - G[c].first,
+                     fetch, G[c].ngrp, smap, smask, sops, buf, lane);
   }
 }
 
@@ -792,6 +855,38 @@ hipError_t launch3_dma(const Lvl3& L, const double* qo, double* qn, double* res,
 }
 
 template <int N>
+hipError_t launch3_group(const Member3* G, int nm, long long total, double A, double B,
+                         double dt, double tau, double cs, hipStream_t st) {
+  using D = Dims3<N>;
+  constexpr int Nfp = D::Nfp;
+  const size_t lds = sizeof(double) * ((4 * Nfp + 96 * Nfp + 1) / 2 + D::NFRAG * 16) +
+                     (size_t)kWavesR * BufR<N>::BYTES;
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_level3_dma_group<N>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3_dma_group<N>,
+                                                       kWavesR * 64, lds);
+    if (e != hipSuccess) return e;
+    resident = std::max(1, per_cu) * prop.multiProcessorCount;
+  }
+  const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, total) / 8 * 8);
+  hipLaunchKernelGGL(k_level3_dma_group<N>, dim3(blocks), dim3(kWavesR * 64), lds, st, G, nm,
+                     total, A, B, dt, tau, cs);
+  return hipGetLastError();
+}
+
+template <int N>
 hipError_t launch3_reg(const Lvl3& L, const double* qo, double* qn, double* res,
                        const double* qb3, double A, double B, double dt, const Shots& sh,
                        hipStream_t st) {
@@ -851,6 +946,17 @@ hipError_t launch_level3(const Lvl3& L, const double* qo, double* qn, double* re
     case 4: return launch3<4>(L, qo, qn, res, qb3, A, B, dt, sh, st);
     case 5: return launch3<5>(L, qo, qn, res, qb3, A, B, dt, sh, st);
     case 6: return launch3<6>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_level3_group(const Member3* G, int nm, long long total, int N, double A,
+                               double B, double dt, double tau, double cs, hipStream_t st) {
+  switch (N) {
+    case 1: return launch3_group<1>(G, nm, total, A, B, dt, tau, cs, st);
+    case 2: return launch3_group<2>(G, nm, total, A, B, dt, tau, cs, st);
+    case 3: return launch3_group<3>(G, nm, total, A, B, dt, tau, cs, st);
+    case 4: return launch3_group<4>(G, nm, total, A, B, dt, tau, cs, st);
     default: return hipErrorInvalidValue;
   }
 }
