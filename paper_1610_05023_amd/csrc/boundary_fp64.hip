@@ -2,10 +2,10 @@
 // the volume and face updates): the 1D edge systems with the edge
 // compatibility systems, and the corner systems.
 //
-// Every block works on one line group of the work list: its lines one
-// after the other, then its corners.  A group holds the three lines of each
-// of its corners, so the new 1D traces a corner system needs are produced
-// by the same block; the new 2D traces the edge systems need come from the
+// One block per line (the lines of a stage are independent: each reads the
+// stage-start states of its neighbours and the corner r- of the previous
+// stage), then one block per corner in a second launch, which reads the new
+// line-end values; the new 2D traces the edge systems need come from the
 // face kernel launched before.
 //
 // Discretisation as for the volume (Section 3.2), with the face system
@@ -15,6 +15,8 @@
 // the stored pressures p_i = p*_i + S and p_ij = p*_ij + C_ji S_A,i + C_ij S_B,j
 // (Section 3.1), and the characteristic fluxes with Z = rho c.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "levels.hpp"
 
@@ -58,12 +60,10 @@ struct Bufs {
   double *q1n, *res1, *qb1, *q02;
 };
 
-// One block per line group: its lines, then its corners.  NPT edge nodes
-// per thread (NPT 512 >= P^2 Np1).
+// One block per line.  NPT edge nodes per thread (NPT 512 >= P^2 Np1).
 template <int NPT>
-__global__ void __launch_bounds__(512, 4) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, Lvl0 L0, int np3,
-                                                     Bufs b, Shots sh, double A, double B,
-                                                     double dt) {
+__global__ void __launch_bounds__(512, 4) k_boundary(Lvl2 L2, Lvl1 L1, int np3, Bufs b, Shots sh,
+                                                     double A, double B, double dt) {
   extern __shared__ double smem[];
   {
     // this block's shot
@@ -85,9 +85,9 @@ __global__ void __launch_bounds__(512, 4) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, L
   // Every phase issues all of a thread's global loads before its first
   // global store, so that they are in flight together (the state arrays may
   // alias as far as the compiler knows); small constant tables sit in LDS.
-  if (W.maxlin == 0 || W.lines[blk * W.maxlin] < 0 || P == 0) return;
+  if (blk >= L1.Kl || P == 0) return;
   // ---------------------------------------------------------------- 1D ----
-  const int PP = P * P, Np = L1.Np, n2 = 2 * P, n3 = 3 * PP, mc = W.maxcor;
+  const int PP = P * P, Np = L1.Np, n2 = 2 * P;
   double* cDr = smem;                  // Np x Np
   double* cLF = cDr + Np * Np;         // Np x 2
   double* cG = cLF + 2 * Np;           // 2P x 2P
@@ -101,10 +101,6 @@ __global__ void __launch_bounds__(512, 4) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, L
   double* srp = sw + PP * Np;          // 2P x Np
   double* sb = srp + n2 * Np;          // 2P x Np
   double* sS = sb + n2 * Np;           // 2P x Np
-  double* sC = sS + n2 * Np;           // maxcor x 3 x PP x 2 (corner ends: p, w)
-  double* srp0 = sC + mc * 3 * PP * 2; // 3 PP
-  double* sred = srp0 + n3;            // nth partial sums of the corner systems
-  int* cInfo = reinterpret_cast<int*>(sred + nth);   // maxcor x 3: line << 1 | end
   for (int x = tid; x < Np * Np + 2 * Np; x += nth) cDr[x] = L1.ops[x];
   for (int x = tid; x < n2 * n2; x += nth) {
     cG[x] = L1.G[x];
@@ -115,13 +111,8 @@ __global__ void __launch_bounds__(512, 4) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, L
     cCij[x] = L1.Cij[x];
   }
   for (int x = tid; x < P; x += nth) cg[x] = L1.gamma[x];
-  for (int x = tid; x < mc * 3; x += nth) {
-    const int c = W.corners[blk * mc + x / 3];
-    cInfo[x] = c < 0 ? -1 : (L0.info[(c * 3 + x % 3) * 2] << 1) | L0.info[(c * 3 + x % 3) * 2 + 1];
-  }
-  for (int li = 0; li < W.maxlin; ++li) {
-    const int l = W.lines[blk * W.maxlin + li];
-    if (l < 0) break;
+  {
+    const int l = blk;
     __syncthreads();
     for (int x = tid; x < PP * 2 * Np; x += nth) sq[x] = b.q1o[(size_t)l * PP * 2 * Np + x];
     const double rx = L1.geo[l * 4 + 0], irho = L1.geo[l * 4 + 1], Kb = L1.geo[l * 4 + 2],
@@ -245,30 +236,33 @@ __global__ void __launch_bounds__(512, 4) k_boundary(LvlB W, Lvl2 L2, Lvl1 L1, L
       const double p = sps[s * Np + a] + cCji[i * P + j] * sS[i * Np + a] +
                        cCij[i * P + j] * sS[(P + j) * Np + a];
       b.q1n[(((size_t)l * PP + s) * 2) * Np + a] = p;
-      // keep the corner-end values for the corner systems of this block
-      if (a == 0 || a == Np - 1) {
-        const int key = (l << 1) | (a == 0 ? 0 : 1);
-        for (int y = 0; y < mc * 3; ++y)
-          if (cInfo[y] == key) {
-            sC[(y * PP + s) * 2] = p;
-            sC[(y * PP + s) * 2 + 1] = sw[s * Np + a];
-          }
-      }
     }
   }
-  // ---------------------------------------------------------------- 0D ----
-  // r- = T r+ with the 3P^2 x 3P^2 corner map; the products are split over
-  // the block (nparts partial sums per output) and reduced in LDS
+}
+
+// ---------------------------------------------------------------- 0D ----
+// One block per corner: r+ from the new ends of its three lines, then
+// r- = T r+ with the 3P^2 x 3P^2 corner map; the products are split over
+// the block (nparts partial sums per output) and reduced in LDS.
+__global__ void __launch_bounds__(512) k_corners(Lvl1 L1, Lvl0 L0, Bufs b, Shots sh) {
+  extern __shared__ double smem[];
+  {
+    const size_t k = blockIdx.y;   // this block's shot
+    b.q1n += k * sh.st1;
+    b.qb1 += k * sh.stb1;
+  }
+  const int P = L1.P, PP = P * P, n3 = 3 * PP, Np = L1.Np;
+  const int tid = threadIdx.x, nth = blockDim.x, c = blockIdx.x;
+  double* srp0 = smem;         // 3 PP
+  double* sred = srp0 + n3;    // max(nth, n3) partial sums
   const int nparts = nth / n3 > 0 ? nth / n3 : 1;
-  for (int ci = 0; ci < mc; ++ci) {
-    const int c = W.corners[blk * mc + ci];
-    if (c < 0) break;
-    __syncthreads();
+  {
     for (int y = tid; y < n3; y += nth) {
-      const int cs = y / PP;
-      const int l = cInfo[ci * 3 + cs] >> 1;
-      srp0[y] = 0.5 * (sC[(ci * 3 * PP + y) * 2] +
-                       L1.geo[l * 4 + 3] * L0.nrm[c * 3 + cs] * sC[(ci * 3 * PP + y) * 2 + 1]);
+      const int cs = y / PP, s = y - cs * PP;
+      const int l = L0.info[(c * 3 + cs) * 2], end = L0.info[(c * 3 + cs) * 2 + 1];
+      const int node = end ? Np - 1 : 0;
+      const double* q = b.q1n + (((size_t)l * PP + s) * 2) * Np;
+      srp0[y] = 0.5 * (q[node] + L1.geo[l * 4 + 3] * L0.nrm[c * 3 + cs] * q[Np + node]);
     }
     __syncthreads();
     for (int y = tid; y < n3 * nparts; y += nth) {
@@ -310,14 +304,14 @@ hipError_t launch_boundary(const LvlB& W, const Lvl2& L2, const Lvl1& L1, const 
                            const double* q1o, double* q1n, double* res1, double* qb1,
                            double* q02, double A, double B, double dt, const Shots& sh,
                            hipStream_t st) {
-  if (W.nblocks == 0) return hipSuccess;
+  (void)W;
+  if (L1.Kl == 0) return hipSuccess;
   if (sh.n < 1 || sh.n > 65535) return hipErrorInvalidValue;
   const int P = L2.P, Np1 = L1.Np, PP = P * P;
   if (P == 0) return hipSuccess;   // no edge or corner systems
   const int n2 = 2 * P, n3 = 3 * PP;
   const size_t a1 = Np1 * Np1 + 2 * Np1 + 2 * n2 * n2 + 2 * PP + P + PP * 2 * Np1 +
-                    2 * PP * Np1 + 3 * n2 * Np1 + W.maxcor * 3 * PP * 2 + n3 + 512 +
-                    (W.maxcor * 3 + 1) / 2 + 1;
+                    2 * PP * Np1 + 3 * n2 * Np1;
   Bufs b{q2o, q2n, res2, qb2, qb3, q03, q3n, q1o, q1n, res1, qb1, q02};
   if (PP * Np1 > 1024) return hipErrorInvalidValue;
   const size_t lds = sizeof(double) * a1;
@@ -325,14 +319,22 @@ hipError_t launch_boundary(const LvlB& W, const Lvl2& L2, const Lvl1& L1, const 
   if (PP * Np1 <= 512) {
     hipError_t e = set_lds((const void*)k_boundary<1>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_boundary<1>, dim3(W.nblocks, sh.n), dim3(512), lds, st, W, L2, L1, L0,
-                       L3.Np, b, sh, A, B, dt);
+    hipLaunchKernelGGL(k_boundary<1>, dim3(L1.Kl, sh.n), dim3(512), lds, st, L2, L1, L3.Np, b,
+                       sh, A, B, dt);
   } else {
     hipError_t e = set_lds((const void*)k_boundary<2>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_boundary<2>, dim3(W.nblocks, sh.n), dim3(512), lds, st, W, L2, L1, L0,
-                       L3.Np, b, sh, A, B, dt);
+    hipLaunchKernelGGL(k_boundary<2>, dim3(L1.Kl, sh.n), dim3(512), lds, st, L2, L1, L3.Np, b,
+                       sh, A, B, dt);
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || L0.Kp == 0) return e;
+  // srp0, then the partial sums: nparts n3 <= 512 entries, or n3 when a
+  // corner system is larger than the block (nparts = 1)
+  const size_t lds0 = sizeof(double) * (n3 + std::max(512, n3));
+  e = set_lds((const void*)k_corners, lds0);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_corners, dim3(L0.Kp, sh.n), dim3(512), lds0, st, L1, L0, b, sh);
   return hipGetLastError();
 }
 
