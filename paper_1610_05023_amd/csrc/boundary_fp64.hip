@@ -298,13 +298,12 @@ hipError_t set_lds(const void* fn, size_t bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t launch_boundary(const LvlB& W, const Lvl2& L2, const Lvl1& L1, const Lvl0& L0,
+hipError_t launch_boundary(const Lvl2& L2, const Lvl1& L1, const Lvl0& L0,
                            const Lvl3& L3, const double* q2o, double* q2n, double* res2,
                            double* qb2, double* qb3, double* q03, const double* q3n,
                            const double* q1o, double* q1n, double* res1, double* qb1,
                            double* q02, double A, double B, double dt, const Shots& sh,
                            hipStream_t st) {
-  (void)W;
   if (L1.Kl == 0) return hipSuccess;
   if (sh.n < 1 || sh.n > 65535) return hipErrorInvalidValue;
   const int P = L2.P, Np1 = L1.Np, PP = P * P;

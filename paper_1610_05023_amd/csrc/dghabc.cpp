@@ -37,7 +37,7 @@ struct Layout {
   Region q3[2], res3, geo3, zn3, nbr3, ops3, ops3f, fmask3, fmap3, mass3, J3, esum;
   Region q2[2], res2, qb3, q03, geo2, info2, tetnode2, nbrnode2, ops2, fmask2, gamma;
   Region q1[2], res1, qb2, q02, geo1, info1, trinode1, ops1, cji, cij, G, H;
-  Region qb1, info0, nrm0, T, srcw, srcp, wlines, wcorners, flags, ops2f;
+  Region qb1, info0, nrm0, T, srcw, srcp, flags, ops2f;
   Region mlpw, hist, csamp;   // learned closure: parameters, trace history, samples
   Region clk;                 // device clock of replayed stepping {t0, steps}
   Region grp;                 // member tables of a group step (two parities)
@@ -82,8 +82,6 @@ struct dgh_ctx {
   dgh::Lvl2 L2{};
   dgh::Lvl1 L1{};
   dgh::Lvl0 L0{};
-  dgh::LvlB LB{};
-  std::vector<int> wlines, wcorners;  // line-group work list (host copy)
   bool closure = false;               // learned closure replaces the face level
   bool record = false;                // keep the trace history for sampling
   dgh::LvlF LF{};
@@ -134,59 +132,6 @@ struct HostArrays {
   std::vector<double> nrm0;
   bool map_ok = true;
 };
-
-// Groups the lines that must be updated by one block: lines joined through
-// a corner, so that the corner system sees the new traces of its three
-// lines.  Corner groups come first (they carry the longest chains).
-void build_worklist(dgh_ctx* c) {
-  const dgh::Mesh& m = c->mesh;
-  const int Kl = m.Klin;
-  std::vector<int> parent(Kl);
-  for (int l = 0; l < Kl; ++l) parent[l] = l;
-  auto find = [&](int x) {
-    while (parent[x] != x) x = parent[x] = parent[parent[x]];
-    return x;
-  };
-  auto unite = [&](int a, int b) { parent[find(a)] = find(b); };
-  for (int p = 0; p < m.Kpnt; ++p) {
-    unite(m.pnt_line[3 * p], m.pnt_line[3 * p + 1]);
-    unite(m.pnt_line[3 * p], m.pnt_line[3 * p + 2]);
-  }
-  std::vector<std::vector<int>> glines, gcors;
-  std::vector<int> gid(Kl, -1);
-  for (int l = 0; l < Kl; ++l) {
-    const int r = find(l);
-    if (gid[r] < 0) {
-      gid[r] = (int)glines.size();
-      glines.emplace_back();
-      gcors.emplace_back();
-    }
-    glines[gid[r]].push_back(l);
-  }
-  for (int p = 0; p < m.Kpnt; ++p) gcors[gid[find(m.pnt_line[3 * p])]].push_back(p);
-  std::vector<int> order(glines.size());
-  for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return glines[a].size() > glines[b].size(); });
-  int maxlin = 0, maxcor = 0;
-  for (size_t g = 0; g < glines.size(); ++g) {
-    maxlin = std::max(maxlin, (int)glines[g].size());
-    maxcor = std::max(maxcor, (int)gcors[g].size());
-  }
-  const int nb = (int)glines.size();
-  const int ml = std::max(1, maxlin), mc = std::max(1, maxcor);
-  c->wlines.assign((size_t)std::max(1, nb) * ml, -1);
-  c->wcorners.assign((size_t)std::max(1, nb) * mc, -1);
-  for (int k = 0; k < nb; ++k) {
-    const int g = order[k];
-    for (size_t j = 0; j < glines[g].size(); ++j) c->wlines[(size_t)k * ml + j] = glines[g][j];
-    for (size_t j = 0; j < gcors[g].size(); ++j) c->wcorners[(size_t)k * mc + j] = gcors[g][j];
-  }
-  dgh::LvlB& W = c->LB;
-  W.nblocks = nb;
-  W.maxlin = maxlin;
-  W.maxcor = maxcor;
-}
 
 void build_host_arrays(dgh_ctx* c, HostArrays& h) {
   const dgh::Mesh& m = c->mesh;
@@ -405,8 +350,6 @@ void build_host_arrays(dgh_ctx* c, HostArrays& h) {
   h.ops1 = m.line.Dr;
   h.ops1.insert(h.ops1.end(), m.line.LIFT.begin(), m.line.LIFT.end());
   (void)Np1;
-  // ---- work list of the boundary kernel
-  build_worklist(c);
   // ---- 0D
   h.info0.assign((size_t)m.Kpnt * 6, 0);
   h.nrm0 = m.pnt_nrm;
@@ -480,9 +423,6 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.T, (size_t)std::max(1, 9 * P * P * P * P) * d);
   L.add(L.srcw, S * Np * d);
   L.add(L.srcp, S * 4 * d);
-  build_worklist(c);
-  L.add(L.wlines, std::max<size_t>(1, c->wlines.size()) * i4);
-  L.add(L.wcorners, std::max<size_t>(1, c->wcorners.size()) * i4);
   L.add(L.flags, (size_t)dgh::kScanMax * dgh::kScanBlocks * i4);
   L.add(L.ops2f, (size_t)dgh::frag2_size(m.N) * d);
   const size_t nnode = (size_t)std::max(1, Kt * Np2);
@@ -553,8 +493,6 @@ void fill_levels(dgh_ctx* c) {
   z.Tt = dptr<double>(c, L.T);
   c->LF.np3 = m.tet.Np;
   c->LF.ops = dptr<double>(c, L.ops2f);
-  c->LB.lines = dptr<int>(c, L.wlines);
-  c->LB.corners = dptr<int>(c, L.wcorners);
 }
 
 // canonical [K][4][Np] <-> device [tile][4][Np][16] in slot order
@@ -762,8 +700,6 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
       for (int k = 0; k < n3; ++k) Tt[(size_t)k * n3 + r] = c->habc.T[(size_t)r * n3 + k];
     HIPCHECK(c, upload(c, L.T, Tt));
   }
-  HIPCHECK(c, upload(c, L.wlines, c->wlines));
-  HIPCHECK(c, upload(c, L.wcorners, c->wcorners));
   HIPCHECK(c, upload(c, L.ops2f, h.ops2f));
   fill_levels(c);
   c->cur = 0;
@@ -965,7 +901,7 @@ dgh_status enqueue_step(dgh_ctx* c, double dt, double t, hipStream_t st, double*
                              dptr<double>(c, L.qb2), L.e3 == 4 ? 1 : 0};
       HIPCHECK(c, dgh::launch_faces(c->LF, c->L2, fb, sh, kA[s], kB[s], dt, st));
     }
-    HIPCHECK(c, dgh::launch_boundary(c->LB, c->L2, c->L1, c->L0, c->L3, dptr<double>(c, L.q2[o]),
+    HIPCHECK(c, dgh::launch_boundary(c->L2, c->L1, c->L0, c->L3, dptr<double>(c, L.q2[o]),
                                      dptr<double>(c, L.q2[n]), dptr<double>(c, L.res2),
                                      dptr<double>(c, L.qb2), dptr<double>(c, L.qb3),
                                      dptr<double>(c, L.q03), dptr<double>(c, L.q3[n]),
@@ -1209,7 +1145,7 @@ dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, d
                                dptr<double>(c, L.q03), c->ws + L.q3[nn].off,
                                dptr<double>(c, L.qb2), 0};
         HIPCHECK(c0, dgh::launch_faces(c->LF, c->L2, fb, sh, kA[s], kB[s], dt, st));
-        HIPCHECK(c0, dgh::launch_boundary(c->LB, c->L2, c->L1, c->L0, c->L3,
+        HIPCHECK(c0, dgh::launch_boundary(c->L2, c->L1, c->L0, c->L3,
                                           dptr<double>(c, L.q2[o]), dptr<double>(c, L.q2[nn]),
                                           dptr<double>(c, L.res2), dptr<double>(c, L.qb2),
                                           dptr<double>(c, L.qb3), dptr<double>(c, L.q03),

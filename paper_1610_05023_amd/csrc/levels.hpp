@@ -150,14 +150,9 @@ hipError_t launch_level3_f32(const Lvl3& L, const float* qo, float* qn, float* r
 // Work list of the line-group kernel: block b updates the lines
 // lines[b][*] (each with its edge system), then the corners corners[b][*];
 // -1 ends a list.  A block holds every line of its corners.
-struct LvlB {
-  int nblocks, maxlin, maxcor;
-  const int* lines;
-  const int* corners;
-};
 
 // 1D and 0D levels of one stage (after the 3D and 2D updates).
-hipError_t launch_boundary(const LvlB& W, const Lvl2& L2, const Lvl1& L1, const Lvl0& L0,
+hipError_t launch_boundary(const Lvl2& L2, const Lvl1& L1, const Lvl0& L0,
                            const Lvl3& L3, const double* q2o, double* q2n, double* res2,
                            double* qb2, double* qb3, double* q03, const double* q3n,
                            const double* q1o, double* q1n, double* res1, double* qb1,
