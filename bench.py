@@ -96,20 +96,22 @@ def build_batch_workload(n=20, N=4, P=3, shots=64):
 def run_uneven(args):
     """Uneven batch: meshes of 10^3, 16^3 and 24^3 cells (x 6 tets), N = 4,
     HABC P = 3, rho = c = 1, one Ricker source each at a seeded interior
-    position, FP64; stepped as one group (one 3D launch per stage over all
-    their tiles) and, for comparison, one after the other."""
+    position, FP64 or the FP32 variant (--precision); stepped as one group
+    (one 3D launch per stage over all their tiles) and, for comparison, one
+    after the other."""
     import numpy as np
     import torch
     import workloads as w
     from paper_1610_05023_amd import Solver
     from paper_1610_05023_amd.binding import step_group
     N, P, sizes = 4, 3, (10, 16, 24)
+    prec = 2 if args.precision == "fp32" else 0
     solvers, U = [], 0
     xs = w.shot_positions(len(sizes), seed=6)
     for j, n in enumerate(sizes):
         VX, E = w.kuhn_mesh(n)
         K = E.shape[0]
-        s = Solver(VX, E, N, P, np.ones(K), np.ones(K)).bind()
+        s = Solver(VX, E, N, P, np.ones(K), np.ones(K), precision=prec).bind()
         s.set_source(xs[j], 2.0, 0.625)
         k = s.counts
         U += w.n_unknowns(k["K"], k["Ktri"], k["Klin"], N, P)
@@ -133,8 +135,9 @@ def run_uneven(args):
         "metric": METRIC, "value": U * 5 * args.steps / el, "unit": "DOF-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "uneven group: FP64 DG+HABC steps of three Kuhn meshes of "
+        "vs_baseline": None, "dtype": "f32" if prec else "f64", "data": "synthetic",
+        "config": {"workload": f"uneven group: {'FP32' if prec else 'FP64'} DG+HABC steps of "
+                               "three Kuhn meshes of "
                                "10^3, 16^3 and 24^3 cells x 6 tets stepped together, N=4, HABC "
                                "P=3, rho=c=1, one Ricker source each (seed 6)",
                    "unknowns": U, "dt": dt, "parallelism": "single GPU",

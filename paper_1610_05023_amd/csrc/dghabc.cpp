@@ -1091,10 +1091,11 @@ dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, d
     if (c->stage < S_BOUND) return fail(c0, DGH_ESTATE, "group member not bound");
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return fail(c0, DGH_EINVAL, "a context appears twice in the group");
-    if (c->lay.e3 != 8 || c->N > 4 || c->L3.kvar != 0)
-      return fail(c0, DGH_EINVAL, "group steps need FP64, N <= 4 and the tile-on-chip kernel");
-    if (c->N != c0->N || c->device != c0->device || c->stream != c0->stream)
-      return fail(c0, DGH_EINVAL, "group members need the same N, device and stream");
+    if (c->N > 4 || c->L3.kvar != 0)
+      return fail(c0, DGH_EINVAL, "group steps need N <= 4 and the tile-on-chip kernel");
+    if (c->N != c0->N || c->lay.e3 != c0->lay.e3 || c->device != c0->device ||
+        c->stream != c0->stream)
+      return fail(c0, DGH_EINVAL, "group members need the same N, precision, device and stream");
     if (c->closure || c->record) return fail(c0, DGH_EINVAL, "group steps run the plain method");
   }
   if (n_steps < 0 || !(dt > 0) || !std::isfinite(t_start)) return fail(c0, DGH_EINVAL, "bad step arguments");
@@ -1131,8 +1132,12 @@ dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, d
     const double t = t_start + it * dt;
     for (int s = 0; s < 5; ++s) {
       const int par = (it * 5 + s) & 1;
-      HIPCHECK(c0, dgh::launch_level3_group(dev + par * n, n, total, c0->N, kA[s], kB[s], dt,
-                                            t + kC[s] * dt, kC[s], st));
+      if (c0->lay.e3 == 4)
+        HIPCHECK(c0, dgh::launch_level3_f32_group(dev + par * n, n, total, c0->N, kA[s], kB[s],
+                                                  dt, t + kC[s] * dt, kC[s], st));
+      else
+        HIPCHECK(c0, dgh::launch_level3_group(dev + par * n, n, total, c0->N, kA[s], kB[s], dt,
+                                              t + kC[s] * dt, kC[s], st));
       for (int i = 0; i < n; ++i) {
         dgh_ctx* c = ctxs[i];
         const Layout& L = c->lay;
@@ -1143,7 +1148,7 @@ dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, d
         const dgh::FaceBufs fb{dptr<double>(c, L.q2[o]), dptr<double>(c, L.q2[nn]),
                                dptr<double>(c, L.res2), dptr<double>(c, L.qb3),
                                dptr<double>(c, L.q03), c->ws + L.q3[nn].off,
-                               dptr<double>(c, L.qb2), 0};
+                               dptr<double>(c, L.qb2), L.e3 == 4 ? 1 : 0};
         HIPCHECK(c0, dgh::launch_faces(c->LF, c->L2, fb, sh, kA[s], kB[s], dt, st));
         HIPCHECK(c0, dgh::launch_boundary(c->L2, c->L1, c->L0, c->L3,
                                           dptr<double>(c, L.q2[o]), dptr<double>(c, L.q2[nn]),

@@ -132,9 +132,11 @@ struct Member3 {
   int ngrp;          // tile groups per shot
 };
 constexpr int kMaxGroup = 8;
-// FP64, N <= 4 (the tile-on-chip kernel); G in device memory
+// N <= 4 (the tile-on-chip kernels), FP64 or FP32 state; G in device memory
 hipError_t launch_level3_group(const Member3* G, int nm, long long total, int N, double A,
                                double B, double dt, double tau, double cs, hipStream_t st);
+hipError_t launch_level3_f32_group(const Member3* G, int nm, long long total, int N, double A,
+                                   double B, double dt, double tau, double cs, hipStream_t st);
 
 // the device clock of replayed stepping: clk = {t0, 0}; clk[1] += 1
 hipError_t launch_clock_set(double* clk, double t0, hipStream_t st);

@@ -368,12 +368,14 @@ __device__ __forceinline__ void face_fetch_f(FaceInF<N>& x, int f, int code, int
   }
 }
 
-template <int N>
+// One work item whose tile is in buf; fetch_next() issues the direct loads
+// of the next item (if any) once the tile's copy has been read.
+template <int N, class Fetch>
 __device__ __forceinline__ void tile_f32_dma(const Lvl3& L, const float* __restrict__ qo,
                                              float* __restrict__ qn, float* __restrict__ res,
                                              const double* __restrict__ qb3, float A, float B,
                                              float dt, const Shots& sh, long long item,
-                                             long long next, int ngrp, const int* smap,
+                                             Fetch fetch_next, int ngrp, const int* smap,
                                              const int* smask, const float* sops, char* buf,
                                              int lane) {
   using D = Dims3f<N>;
@@ -392,7 +394,7 @@ __device__ __forceinline__ void tile_f32_dma(const Lvl3& L, const float* __restr
   if (tile >= L.ntile) {
     // no stores follow: wait for the next tile's direct loads here
     __builtin_amdgcn_s_waitcnt(0);
-    if (next >= 0) tile_dma_f<N>(L, qo, sh, next, ngrp, buf, lane);
+    fetch_next();
     __builtin_amdgcn_s_waitcnt(0);
     return;
   }
@@ -495,7 +497,7 @@ __device__ __forceinline__ void tile_f32_dma(const Lvl3& L, const float* __restr
         }
       __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): every LDS read returned
       __builtin_amdgcn_sched_barrier(0);
-      if (next >= 0) tile_dma_f<N>(L, qo, sh, next, ngrp, buf, lane);
+      fetch_next();
       __builtin_amdgcn_sched_barrier(0);
     }
     const FaceInF<N>& x = fb[f];
@@ -628,9 +630,99 @@ __global__ void __launch_bounds__(kWavesF * 64, 1) k_level3_f32_dma(
   __syncthreads();
   for (long long it = rg_.lo; it < rg_.hi; it += rg_.step) {
     const long long nx = it + rg_.step;
-    tile_f32_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, it, nx < rg_.hi ? nx : -1, ngrp, smap,
-                    smask, sops, buf, lane);
+    auto fetch = [&]() {
+      if (nx < rg_.hi) tile_dma_f<N>(L, qo, sh, nx, ngrp, buf, lane);
+    };
+    tile_f32_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, it, fetch, ngrp, smap, smask, sops, buf,
+                    lane);
   }
+}
+
+// The same kernel over a group of contexts (any mesh sizes, same N): one
+// work list, member c owning [first_c, first_c + items_c); the LDS tables
+// and operators depend on N only.
+template <int N>
+__global__ void __launch_bounds__(kWavesF * 64, 1) k_level3_f32_dma_group(
+    const Member3* __restrict__ G, int nm, long long total, float A, float B, float dt,
+    double tau, double cs) {
+  using D = Dims3f<N>;
+  constexpr int Nfp = D::Nfp;
+  extern __shared__ float sfl[];
+  int* smask = reinterpret_cast<int*>(sfl);
+  int* smap = smask + 4 * Nfp;
+  float* sops = sfl + 4 * Nfp + 96 * Nfp;
+  const int lane = threadIdx.x & 63;
+  const XcdRange rg_(total, G[0].L.order);
+  char* buf = reinterpret_cast<char*>(sops + D::NOPS) +
+              __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * BufF<N>::BYTES;
+  auto member = [&](long long it) {
+    int c = 0;
+    while (c + 1 < nm && G[c + 1].first <= it) ++c;
+    return c;
+  };
+  auto shots = [&](int c) {
+    Shots sh = G[c].sh;
+    sh.tau = tau;
+    sh.cs = cs;
+    sh.clk = nullptr;
+    return sh;
+  };
+  if (rg_.lo < rg_.hi) {
+    const int c = member(rg_.lo);
+    tile_dma_f<N>(G[c].L, static_cast<const float*>(G[c].qo), shots(c), rg_.lo - G[c].first,
+                  G[c].ngrp, buf, lane);
+  }
+  fill_lds<kWavesF * 64, 4 * Nfp>(smask, G[0].L.fmask, threadIdx.x);
+  fill_lds<kWavesF * 64, 96 * Nfp>(smap, G[0].L.fmap, threadIdx.x);
+  fill_lds<kWavesF * 64, D::NOPS>(sops, G[0].L.ops32, threadIdx.x);
+  __syncthreads();
+  for (long long it = rg_.lo; it < rg_.hi; it += rg_.step) {
+    const long long nx = it + rg_.step;
+    const int c = member(it);
+    const Shots sh = shots(c);
+    auto fetch = [&]() {
+      if (nx < rg_.hi) {
+        const int cn = member(nx);
+        tile_dma_f<N>(G[cn].L, static_cast<const float*>(G[cn].qo), shots(cn),
+                      nx - G[cn].first, G[cn].ngrp, buf, lane);
+      }
+    };
+    tile_f32_dma<N>(G[c].L, static_cast<const float*>(G[c].qo), static_cast<float*>(G[c].qn),
+                    static_cast<float*>(G[c].res), G[c].qb3, A, B, dt, sh, it - G[c].first,
+                    fetch, G[c].ngrp, smap, smask, sops, buf, lane);
+  }
+}
+
+template <int N>
+hipError_t launch3f_group(const Member3* G, int nm, long long total, double A, double B,
+                          double dt, double tau, double cs, hipStream_t st) {
+  using D = Dims3f<N>;
+  constexpr int Nfp = D::Nfp;
+  const size_t lds = sizeof(float) * (4 * Nfp + 96 * Nfp + D::NOPS) +
+                     (size_t)kWavesF * BufF<N>::BYTES;
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_level3_f32_dma_group<N>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3_f32_dma_group<N>,
+                                                       kWavesF * 64, lds);
+    if (e != hipSuccess) return e;
+    resident = std::max(1, per_cu) * prop.multiProcessorCount;
+  }
+  const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, total) / 8 * 8);
+  hipLaunchKernelGGL(k_level3_f32_dma_group<N>, dim3(blocks), dim3(kWavesF * 64), lds, st, G, nm,
+                     total, (float)A, (float)B, (float)dt, tau, cs);
+  return hipGetLastError();
 }
 
 template <int N>
@@ -706,6 +798,17 @@ hipError_t launch3f(const Lvl3& L, const float* qo, float* qn, float* res, const
 }
 
 }  // namespace
+
+hipError_t launch_level3_f32_group(const Member3* G, int nm, long long total, int N, double A,
+                                   double B, double dt, double tau, double cs, hipStream_t st) {
+  switch (N) {
+    case 1: return launch3f_group<1>(G, nm, total, A, B, dt, tau, cs, st);
+    case 2: return launch3f_group<2>(G, nm, total, A, B, dt, tau, cs, st);
+    case 3: return launch3f_group<3>(G, nm, total, A, B, dt, tau, cs, st);
+    case 4: return launch3f_group<4>(G, nm, total, A, B, dt, tau, cs, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_level3_f32(const Lvl3& L, const float* qo, float* qn, float* res,
                              const double* qb3, double A, double B, double dt, const Shots& sh,

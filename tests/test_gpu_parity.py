@@ -301,13 +301,14 @@ def test_checkpoint_resume_is_bitwise():
         assert np.array_equal(want[k], got[k]), k
 
 
-def test_group_step_equals_separate_runs():
+@pytest.mark.parametrize("precision", [0, 2])
+def test_group_step_equals_separate_runs(precision):
     """An uneven group (meshes of 3^3, 4^3 and 5^3 cells, one of them with
     two shots, the largest in a layered medium, each shot with its own
-    source and random state)
+    source and random state), FP64 or the FP32 variant,
     stepped together -- one 3D launch per stage over all their tiles --
-    equals each context stepped alone, bitwise; a member with another N is
-    refused."""
+    equals each context stepped alone, bitwise; a member with another N or
+    another precision is refused."""
     from paper_1610_05023_amd import Solver
     from paper_1610_05023_amd.binding import DghError, step_group
     N, P, steps, dt = 4, 3, 6, 1e-3
@@ -316,7 +317,8 @@ def test_group_step_equals_separate_runs():
         medium = "layered" if n >= 5 else "const"
         base = make_case(n=n, N=N, P=P, medium=medium, init="zero", seed=seed)
         s = Solver(base["VX"], base["E"], N, P, base["rho"], base["c"], face_bc=base["face_bc"],
-                   periodic=base["periodic"], box=base["box"], n_shots=shots).bind()
+                   periodic=base["periodic"], box=base["box"], n_shots=shots,
+                   precision=precision).bind()
         for k in range(shots):
             c = make_case(n=n, N=N, P=P, medium=medium, init="random", seed=seed + 10 * k + 1,
                           source=((0.41 + 0.1 * k, 0.52, 0.33), 6.0 + k, 0.02))
@@ -339,8 +341,13 @@ def test_group_step_equals_separate_runs():
             got = s.read_fields(shot=k)
             for a in ref[k]:
                 assert np.array_equal(got[a], ref[k][a]), (n, k, a)
-    print(f"[group] {len(specs)} meshes stepped together == separately, bitwise", flush=True)
+    print(f"[group] precision {precision}: {len(specs)} meshes stepped together == "
+          f"separately, bitwise", flush=True)
     other = make_case(n=3, N=3, P=P, init="zero")
-    s3 = make_solver(other)
+    s3 = make_solver(other, precision=precision)
     with pytest.raises(DghError):
         step_group([group[0], s3], 1, dt)
+    same_n = make_case(n=3, N=N, P=P, init="zero")
+    s4 = make_solver(same_n, precision=2 - precision)
+    with pytest.raises(DghError):
+        step_group([group[0], s4], 1, dt)
