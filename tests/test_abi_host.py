@@ -45,6 +45,44 @@ def test_host_setup_matches_oracle(n, N, P, bc):
     assert np.abs(s.node_coords() - o.node_coords()).max() < 1e-14
 
 
+def test_general_mesh_inputs():
+    """The unstructured test mesh: every element positively oriented, the
+    boundary vertices where the Kuhn mesh has them, every face shared by two
+    elements or lying on a box plane; the host setup (general element order)
+    agrees with the oracle on counts, shapes and node coordinates."""
+    from oracle.solver import Oracle
+    from paper_1610_05023_amd import Solver
+    n = 4
+    VX0, E0 = w.kuhn_mesh(n)
+    VX, E = w.general_mesh(n, amp=0.1, seed=5)
+    assert VX.shape == VX0.shape and E.shape == E0.shape
+    on_bnd = np.any((VX0 < 1e-12) | (VX0 > 1 - 1e-12), axis=1)
+    assert np.array_equal(VX[on_bnd], VX0[on_bnd])
+    assert np.abs(VX[~on_bnd] - VX0[~on_bnd]).max() > 0.01 / n
+    d = VX[E[:, 1:]] - VX[E[:, :1]]
+    assert np.linalg.det(d).min() > 0
+    assert not np.array_equal(np.sort(E, axis=1), np.sort(E0, axis=1))
+    assert sorted(map(tuple, np.sort(E, axis=1))) == sorted(map(tuple, np.sort(E0, axis=1)))
+    faces = {}
+    for e in range(E.shape[0]):
+        for f in range(4):
+            key = tuple(sorted(np.delete(E[e], f)))
+            faces[key] = faces.get(key, 0) + 1
+    for key, cnt in faces.items():
+        if cnt == 1:
+            x = VX[list(key)]
+            assert np.any(np.all((x < 1e-12) | (x > 1 - 1e-12), axis=0)), key
+        else:
+            assert cnt == 2, key
+    K = E.shape[0]
+    o = Oracle(VX, E, 3, 2, np.ones(K), np.ones(K))
+    s = Solver(VX, E, 3, 2, np.ones(K), np.ones(K))
+    k = s.counts
+    assert (k["K"], k["Ktri"], k["Klin"], k["Kpnt"]) == (o.m.K, o.m.Ktri, o.m.Klin, o.m.Kpnt)
+    assert s.shapes() == o.shapes()
+    assert np.abs(s.node_coords() - o.node_coords()).max() < 1e-14
+
+
 def test_kuhn_counts():
     from paper_1610_05023_amd import Solver
     n = 5

@@ -94,6 +94,31 @@ def test_mixed_faces_random():
     _check(case, 20, 1e-3)
 
 
+@pytest.mark.parametrize("n", [3, 4])
+def test_general_mesh_random_medium(n):
+    """An unstructured mesh (n^3 Kuhn cells with the interior vertices moved
+    by up to 0.1 h, the elements shuffled, each element's vertices rotated;
+    seed 5) with a random density and wave speed per element: the 3D layout
+    takes the general element order, and the interior faces meet at every
+    vertex permutation.  HABC P = 3 on all faces, random state, a source,
+    30 steps at half the Kuhn time step of the fastest medium.  n = 3 gives
+    162 elements, so the last tile of the layout is ragged."""
+    from oracle.solver import Oracle
+    N, P = 3, 3
+    VX, E = w.general_mesh(n, amp=0.1, seed=5)
+    K = E.shape[0]
+    rng = np.random.default_rng(6)
+    rho, c = rng.uniform(1.0, 2.5, K), rng.uniform(1.0, 3.0, K)
+    fb, per = ("habc",) * 6, (False,) * 3
+    o = Oracle(VX, E, N, P, rho, c, face_bc=fb, periodic=per)
+    state = {k: w.random_array(v, 60 + j) if np.prod(v) else np.zeros(v)
+             for j, (k, v) in enumerate(o.shapes().items())}
+    case = dict(VX=VX, E=E, N=N, P=P, rho=rho, c=c, face_bc=fb, periodic=per, oracle=o,
+                state=state, source=((0.43, 0.55, 0.47), 4.0, 0.1),
+                box=np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0]))
+    _check(case, 30, 0.5 * w.kuhn_dt(n, N, 3.0))
+
+
 def test_energy_matches_oracle():
     case = make_case(n=4, N=3, P=3, init="random", seed=41)
     s = make_solver(case)

@@ -79,6 +79,29 @@ def kuhn_mesh(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), dims=None):
     return VX, EToV.reshape(ncell * 6, 4).astype(np.int32)
 
 
+def general_mesh(n, amp=0.1, seed=0, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
+    """An unstructured tetrahedral mesh of the box: the Kuhn mesh of n^3
+    cells with every interior vertex moved by U(-amp, amp) * h per
+    coordinate, the elements listed in a random order, and each element's
+    vertices rotated by a random even permutation (orientation kept).
+    Vertices on the boundary stay on the boundary grid, so the boundary
+    faces, edges and corners are those of the Kuhn mesh.  Returns (VX, EToV)
+    as ``kuhn_mesh`` does."""
+    VX, E = kuhn_mesh(n, lo=lo, hi=hi)
+    rng = np.random.default_rng(seed)
+    lo_, hi_ = np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
+    h = (hi_ - lo_) / n
+    tol = 1e-9 * h
+    inner = np.all((VX > lo_ + tol) & (VX < hi_ - tol), axis=1)
+    VX = VX.copy()
+    VX[inner] += rng.uniform(-amp, amp, size=(int(inner.sum()), 3)) * h
+    even = [p for p in itertools.permutations(range(4)) if _perm_sign(p) > 0]
+    pick = rng.integers(0, len(even), size=E.shape[0])
+    E = np.stack([E[k, list(even[pick[k]])] for k in range(E.shape[0])])
+    E = E[rng.permutation(E.shape[0])]
+    return VX, np.ascontiguousarray(E, dtype=np.int32)
+
+
 def cell_index_of_element(n, dims=None):
     """(i, j, k) cell indices of every element of ``kuhn_mesh``."""
     nx, ny, nz = dims if dims is not None else (n, n, n)
