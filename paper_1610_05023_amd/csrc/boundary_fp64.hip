@@ -18,6 +18,7 @@
 
 #include <algorithm>
 
+#include "launch.hpp"
 #include "levels.hpp"
 
 namespace dgh {
@@ -283,21 +284,6 @@ __global__ void __launch_bounds__(512) k_corners(Lvl1 L1, Lvl0 L0, Bufs b, Shots
 
 }  // namespace
 
-// Raises the dynamic LDS limit of a kernel when a launch needs more.
-hipError_t set_lds(const void* fn, size_t bytes) {
-  static const void* fns[8] = {};
-  static size_t have[8] = {};
-  for (int i = 0; i < 8; ++i) {
-    if (fns[i] == fn && bytes <= have[i]) return hipSuccess;
-    if (fns[i] == fn || !fns[i]) {
-      fns[i] = fn;
-      have[i] = bytes;
-      return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    }
-  }
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
-
 hipError_t launch_boundary(const Lvl2& L2, const Lvl1& L1, const Lvl0& L0,
                            const Lvl3& L3, const double* q2o, double* q2n, double* res2,
                            double* qb2, double* qb3, double* q03, const double* q3n,
@@ -316,12 +302,12 @@ hipError_t launch_boundary(const Lvl2& L2, const Lvl1& L1, const Lvl0& L0,
   const size_t lds = sizeof(double) * a1;
   // one edge node per thread unless P^2 Np1 exceeds the block (P > 10)
   if (PP * Np1 <= 512) {
-    hipError_t e = set_lds((const void*)k_boundary<1>, lds);
+    hipError_t e = kernel_setup((const void*)k_boundary<1>, 512, lds, nullptr);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_boundary<1>, dim3(L1.Kl, sh.n), dim3(512), lds, st, L2, L1, L3.Np, b,
                        sh, A, B, dt);
   } else {
-    hipError_t e = set_lds((const void*)k_boundary<2>, lds);
+    hipError_t e = kernel_setup((const void*)k_boundary<2>, 512, lds, nullptr);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_boundary<2>, dim3(L1.Kl, sh.n), dim3(512), lds, st, L2, L1, L3.Np, b,
                        sh, A, B, dt);
@@ -331,7 +317,7 @@ hipError_t launch_boundary(const Lvl2& L2, const Lvl1& L1, const Lvl0& L0,
   // srp0, then the partial sums: nparts n3 <= 512 entries, or n3 when a
   // corner system is larger than the block (nparts = 1)
   const size_t lds0 = sizeof(double) * (n3 + std::max(512, n3));
-  e = set_lds((const void*)k_corners, lds0);
+  e = kernel_setup((const void*)k_corners, 512, lds0, nullptr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_corners, dim3(L0.Kp, sh.n), dim3(512), lds0, st, L1, L0, b, sh);
   return hipGetLastError();

@@ -27,6 +27,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "launch.hpp"
 #include "levels.hpp"
 
 namespace dgh {
@@ -495,14 +496,10 @@ hipError_t launch_closure(const Lvl2& L2, const float* W, const void* q3, int q3
   if (nn == 0) return hipSuccess;
   const int tiles = (nn + 15) / 16;
   // persistent over the tiles of each shot: about 3 workgroups per CU in all
-  static int cus = 0;
-  if (!cus) {
-    int dev = 0;
-    hipDeviceProp_t prop;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
+  int cus = 0;
+  {
+    const hipError_t e = device_cus(&cus);
     if (e != hipSuccess) return e;
-    cus = prop.multiProcessorCount;
   }
   const int per_shot = std::max(1, 3 * cus / std::max(1, sh.n));
   const dim3 g(std::min((tiles + kCW - 1) / kCW, per_shot), sh.n), b(kCW * 64);

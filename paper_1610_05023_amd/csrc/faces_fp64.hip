@@ -19,6 +19,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "launch.hpp"
 #include "levels.hpp"
 
 namespace dgh {
@@ -303,16 +304,10 @@ hipError_t launch_faces_t(const LvlF& F, const Lvl2& L2, const FaceBufs& b, cons
                           double A, double B, double dt, int ngrp, hipStream_t st) {
   // persistent grid: as many workgroups as fit on the device at once (a
   // multiple of 8, so that every XCD has blocks for its range)
-  static int resident = 0;
-  if (!resident) {
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_faces<N, T3>, kWaves2 * 64, 0);
+  int resident = 0;
+  {
+    const hipError_t e = kernel_setup((const void*)(k_faces<N, T3>), kWaves2 * 64, 0, &resident);
     if (e != hipSuccess) return e;
-    resident = std::max(1, per_cu) * prop.multiProcessorCount;
   }
   const long long items = (long long)ngrp * sh.n;
   const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, items) / 8 * 8);

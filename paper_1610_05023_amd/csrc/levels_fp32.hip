@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "launch.hpp"
 #include "levels.hpp"
 
 namespace dgh {
@@ -700,24 +701,11 @@ hipError_t launch3f_group(const Member3* G, int nm, long long total, double A, d
   constexpr int Nfp = D::Nfp;
   const size_t lds = sizeof(float) * (4 * Nfp + 96 * Nfp + D::NOPS) +
                      (size_t)kWavesF * BufF<N>::BYTES;
-  static bool attr = false;
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_level3_f32_dma_group<N>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int resident = 0;
+  {
+    const hipError_t e =
+        kernel_setup((const void*)(k_level3_f32_dma_group<N>), kWavesF * 64, lds, &resident);
     if (e != hipSuccess) return e;
-    attr = true;
-  }
-  static int resident = 0;
-  if (!resident) {
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3_f32_dma_group<N>,
-                                                       kWavesF * 64, lds);
-    if (e != hipSuccess) return e;
-    resident = std::max(1, per_cu) * prop.multiProcessorCount;
   }
   const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, total) / 8 * 8);
   hipLaunchKernelGGL(k_level3_f32_dma_group<N>, dim3(blocks), dim3(kWavesF * 64), lds, st, G, nm,
@@ -732,26 +720,13 @@ hipError_t launch3f_dma(const Lvl3& L, const float* qo, float* qn, float* res, c
   constexpr int Nfp = D::Nfp;
   const size_t lds = sizeof(float) * (4 * Nfp + 96 * Nfp + D::NOPS) +
                      (size_t)kWavesF * BufF<N>::BYTES;
-  static bool attr = false;
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_level3_f32_dma<N>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
   if (sh.n < 1) return hipErrorInvalidValue;
   const int ngrp = (L.ntile + kWavesF - 1) / kWavesF;
-  static int resident = 0;
-  if (!resident) {
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3_f32_dma<N>, kWavesF * 64,
-                                                       lds);
+  int resident = 0;
+  {
+    const hipError_t e =
+        kernel_setup((const void*)(k_level3_f32_dma<N>), kWavesF * 64, lds, &resident);
     if (e != hipSuccess) return e;
-    resident = std::max(1, per_cu) * prop.multiProcessorCount;
   }
   const long long items = (long long)ngrp * sh.n;
   const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, items) / 8 * 8);
@@ -769,26 +744,13 @@ hipError_t launch3f(const Lvl3& L, const float* qo, float* qn, float* res, const
   using D = Dims3f<N>;
   constexpr int Nfp = D::Nfp;
   const size_t lds = sizeof(float) * (4 * Nfp + 96 * Nfp + (D::kLds ? D::NOPS : 0));
-  static bool attr = false;
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_level3_f32<N>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
   const int ngrp = (L.ntile + kWaves3f - 1) / kWaves3f;
   if (sh.n < 1) return hipErrorInvalidValue;
-  static int resident = 0;
-  if (!resident) {
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3_f32<N>, kWaves3f * 64,
-                                                       lds);
+  int resident = 0;
+  {
+    const hipError_t e =
+        kernel_setup((const void*)(k_level3_f32<N>), kWaves3f * 64, lds, &resident);
     if (e != hipSuccess) return e;
-    resident = std::max(1, per_cu) * prop.multiProcessorCount;
   }
   const long long items = (long long)ngrp * sh.n;
   const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, items) / 8 * 8);

@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "launch.hpp"
 #include "levels.hpp"
 
 namespace dgh {
@@ -827,25 +828,12 @@ hipError_t launch3_dma(const Lvl3& L, const double* qo, double* qn, double* res,
   constexpr int Nfp = D::Nfp;
   const size_t lds = sizeof(double) * ((4 * Nfp + 96 * Nfp + 1) / 2 + D::NFRAG * 16) +
                      (size_t)kWavesR * BufR<N>::BYTES;
-  static bool attr = false;
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_level3_dma<N>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
   const int ngrp = (L.ntile + kWavesR - 1) / kWavesR;
   if (sh.n < 1) return hipErrorInvalidValue;
-  static int resident = 0;
-  if (!resident) {
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3_dma<N>, kWavesR * 64, lds);
+  int resident = 0;
+  {
+    const hipError_t e = kernel_setup((const void*)(k_level3_dma<N>), kWavesR * 64, lds, &resident);
     if (e != hipSuccess) return e;
-    resident = std::max(1, per_cu) * prop.multiProcessorCount;
   }
   const long long items = (long long)ngrp * sh.n;
   const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, items) / 8 * 8);
@@ -861,24 +849,11 @@ hipError_t launch3_group(const Member3* G, int nm, long long total, double A, do
   constexpr int Nfp = D::Nfp;
   const size_t lds = sizeof(double) * ((4 * Nfp + 96 * Nfp + 1) / 2 + D::NFRAG * 16) +
                      (size_t)kWavesR * BufR<N>::BYTES;
-  static bool attr = false;
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_level3_dma_group<N>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  int resident = 0;
+  {
+    const hipError_t e =
+        kernel_setup((const void*)(k_level3_dma_group<N>), kWavesR * 64, lds, &resident);
     if (e != hipSuccess) return e;
-    attr = true;
-  }
-  static int resident = 0;
-  if (!resident) {
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3_dma_group<N>,
-                                                       kWavesR * 64, lds);
-    if (e != hipSuccess) return e;
-    resident = std::max(1, per_cu) * prop.multiProcessorCount;
   }
   const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, total) / 8 * 8);
   hipLaunchKernelGGL(k_level3_dma_group<N>, dim3(blocks), dim3(kWavesR * 64), lds, st, G, nm,
@@ -893,26 +868,13 @@ hipError_t launch3_reg(const Lvl3& L, const double* qo, double* qn, double* res,
   using D = Dims3<N>;
   constexpr int Nfp = D::Nfp;
   const size_t lds = sizeof(double) * ((4 * Nfp + 96 * Nfp + 1) / 2 + (D::kLds ? D::NFRAG * 16 : 0));
-  static bool attr = false;
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_level3<N>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
   const int ngrp = (L.ntile + kWaves3 - 1) / kWaves3;
   if (sh.n < 1) return hipErrorInvalidValue;
   // persistent grid: as many workgroups as fit on the device at once
-  static int resident = 0;
-  if (!resident) {
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipGetDeviceProperties(&prop, dev);
-    if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_level3<N>, kWaves3 * 64, lds);
+  int resident = 0;
+  {
+    const hipError_t e = kernel_setup((const void*)(k_level3<N>), kWaves3 * 64, lds, &resident);
     if (e != hipSuccess) return e;
-    resident = std::max(1, per_cu) * prop.multiProcessorCount;
   }
   const long long items = (long long)ngrp * sh.n;
   // a multiple of 8, so that every XCD has blocks for its range of items
@@ -964,16 +926,10 @@ hipError_t launch_level3_group(const Member3* G, int nm, long long total, int N,
 hipError_t launch_energy(const Lvl3& L, const void* q, int q_f32, const double* mass,
                          const double* J, double* out, hipStream_t st) {
   const size_t lds = sizeof(double) * ((size_t)L.Np * L.Np + 4 * L.Np * kTile + 256);
-  static bool attr = false;   // N = 6 needs more than the default 64 KB
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_energy<float>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_energy<double>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  // N = 6 needs more than the default 64 KB
+  const hipError_t e = kernel_setup(
+      q_f32 ? (const void*)k_energy<float> : (const void*)k_energy<double>, 256, lds, nullptr);
+  if (e != hipSuccess) return e;
   if (q_f32)
     hipLaunchKernelGGL(k_energy<float>, dim3(L.ntile), dim3(256), lds, st, L,
                        static_cast<const float*>(q), mass, J, out);

@@ -119,6 +119,41 @@ def test_general_mesh_random_medium(n):
     _check(case, 30, 0.5 * w.kuhn_dt(n, N, 3.0))
 
 
+def test_contexts_in_two_threads():
+    """Two contexts (N = 3 and N = 4, random states) stepped at the same time
+    from two host threads end where each ends when stepped alone, bitwise:
+    contexts share no state (the launch set-up is kept per device and
+    kernel behind a lock)."""
+    import threading
+    cases = [make_case(n=3, N=3, P=2, init="random", seed=71),
+             make_case(n=3, N=4, P=3, init="random", seed=72)]
+    solvers = [make_solver(c) for c in cases]
+    errs = []
+
+    def run(s):
+        try:
+            s.step(30, 1e-3)
+        except Exception as e:  # reported below
+            errs.append(e)
+
+    th = [threading.Thread(target=run, args=(s,)) for s in solvers]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=60)
+    assert not any(t.is_alive() for t in th) and not errs, errs
+    for c, s in zip(cases, solvers):
+        got = s.read_fields()
+        s.close()
+        alone = make_solver(c)
+        alone.step(30, 1e-3)
+        ref = alone.read_fields()
+        alone.close()
+        for a in ref:
+            assert np.array_equal(got[a], ref[a]), (c["N"], a)
+    print("[threads] two contexts stepped concurrently == alone, bitwise", flush=True)
+
+
 def test_energy_matches_oracle():
     case = make_case(n=4, N=3, P=3, init="random", seed=41)
     s = make_solver(case)
