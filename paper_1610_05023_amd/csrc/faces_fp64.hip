@@ -2,8 +2,9 @@
 // Algorithm 3) on the FP64 4x4x4 MFMA: one wave updates the P auxiliary
 // sets of TW = 16 / P consecutive triangles (MFMA column es = local
 // triangle * P + set), then applies the face rule.  Every load of a wave is
-// issued before its first MFMA: two dependent rounds (triangle data, then
-// what the maps point to).
+// issued before its first MFMA, in two dependent rounds: the wave's q2 and
+// res2 spans (direct buffer-to-LDS loads) with the triangle data, then what
+// the maps point to.
 //
 // Per triangle and set i, with K_i = rho c^2 / (1 + g_i) and the in-plane
 // reference gradients (rx, ry), (sx, sy):
@@ -35,7 +36,20 @@ struct Dims2 {
   static constexpr int RG = (Np + 3) / 4;    // row groups, also volume k-steps
   static constexpr int EK = (Nfp + 3) / 4;   // lifting k-steps per edge
   static constexpr int NFRAG = 2 * RG * RG + RG * 3 * EK;
+  static constexpr int SPAN = 16 * 3 * Np;   // doubles of at most 16 (triangle, set) pairs
+  // bytes of one LDS copy of a span (q2 or res2): whole 1 KB chunks of the
+  // direct loads, with room for a span starting 8 bytes past a 16-byte boundary
+  static constexpr int SB = ((SPAN + 1) * 8 + 1023) / 1024 * 1024;
 };
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+using Rsrc = __amdgpu_buffer_rsrc_t;
+
+// Raw buffer descriptor over [p, p + bytes): loads past the end read 0.
+__device__ __forceinline__ Rsrc span_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
 
 // One work item: the kWaves2 wave slots of group bx of shot k (each wave
 // its TW triangles).  T3: type of the 3D state (double, or float for the
@@ -44,12 +58,10 @@ template <int N, class T3>
 __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBufs b,
                                            const Shots& sh, double A, double B, double dt,
                                            int bx, int k, const double* sops, const double* sg,
-                                           const int* smask,
-                                           double (*sbuf)[2][16 * 3 * Dims2<N>::Np]) {
+                                           const int* smask, char* stage) {
   using D = Dims2<N>;
   constexpr int Np = D::Np, Nfp = D::Nfp, RG = D::RG, EK = D::EK;
-  constexpr int SPAN = 16 * 3 * Np;          // fields of at most 16 (triangle, set) pairs
-  constexpr int KL = (SPAN + 63) / 64;       // linear loads per lane
+  constexpr int KL = (D::SPAN + 63) / 64;    // 64-lane chunks of a span
   const int P = L2.P;
   {
     b.q2o += k * sh.st2;
@@ -60,7 +72,8 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
     b.q3n = static_cast<const T3*>(b.q3n) + k * sh.st3;
     b.qb2 += (size_t)k * sh.stb2;
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int es = lane & 15, g = lane >> 4;
   const int ta = (lane & 3) + 4 * g;         // lane's entry of an A fragment
   const int Pc = P > 0 ? P : 1, TW = 16 / Pc;
@@ -71,19 +84,31 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
   const bool col = tl < ntw;                         // column holds (triangle, set)
   const int t = w0 + min(tl, ntw - 1);
   const int ic = P > 0 ? i : 0;
-  // ---- the wave's pairs are contiguous in q2 and res2: staged through LDS
-  // with linear (coalesced) loads and, at the end, stores
-  double* sq = sbuf[wv][0];
-  double* sr = sbuf[wv][1];
+  // ---- the wave's pairs are contiguous in q2 and res2: copied into this
+  // wave's LDS stage by direct buffer-to-LDS loads (16 bytes per lane from
+  // the 16-byte boundary at or before the span; the descriptors end with the
+  // span) and, at the end, stored back with linear (coalesced) stores
+  char* stq = stage + (size_t)wv * 2 * D::SB;
+  char* str = stq + D::SB;
   const int cnt = ntw * P * 3 * Np;
   const size_t wbase = (size_t)w0 * P * 3 * Np;
+  const int shq = (int)((reinterpret_cast<size_t>(b.q2o + wbase) >> 3) & 1);
+  const int shr = (int)((reinterpret_cast<size_t>(b.res2 + wbase) >> 3) & 1);
+  double* sq = reinterpret_cast<double*>(stq) + shq;
+  double* sr = reinterpret_cast<double*>(str) + shr;
   if (P > 0) {
-    double vq[KL];
-#pragma unroll
-    for (int k = 0; k < KL; ++k) vq[k] = b.q2o[wbase + min(lane + 64 * k, cnt - 1)];
-#pragma unroll
-    for (int k = 0; k < KL; ++k)
-      if (lane + 64 * k < cnt) sq[lane + 64 * k] = vq[k];
+    const unsigned bq = (unsigned)(cnt + shq) * 8, br = (unsigned)(cnt + shr) * 8;
+    const Rsrc Rq = span_rsrc(b.q2o + wbase - shq, bq), Rr = span_rsrc(b.res2 + wbase - shr, br);
+    // the previous item's reads of this stage have returned before it is
+    // overwritten (direct loads write LDS outside the LDS queue)
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+    const int chunks = (int)((std::max(bq, br) + 1023) >> 10);
+    for (int c = 0; c < chunks; ++c) {
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(Rq, (lds_ptr)(stq + c * 1024), 16, lane * 16,
+                                               c * 1024, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(Rr, (lds_ptr)(str + c * 1024), 16, lane * 16,
+                                               c * 1024, 0, 0);
+    }
   }
   // ---- every other load that depends on the triangle only
   const double* gg = L2.geo + (size_t)t * 8;
@@ -107,6 +132,11 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
     n3[r] = L2.tetnode[(size_t)t * Np + n];
     S0[r] = b.q03[(size_t)t * Np + n];
   }
+  // the direct loads and the triangle data have landed (the compiler does not
+  // order LDS reads after direct-to-LDS loads by itself; the map loads below
+  // need the triangle data anyway)
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_sched_barrier(0);
   // ---- loads through the maps: new 3D trace, exterior values of the edges
   double p3[RG], u3[RG];
   {
@@ -118,8 +148,9 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
     }
   }
   // every load is issued at an address valid for any edge kind (own
-  // triangle, line 0 of qb2) and the values are selected afterwards, so
-  // that no load waits behind a branch on loaded data
+  // triangle, line 0 of qb2) and the values are selected afterwards by bit
+  // masks: a select on a loaded value lets the compiler move the load into
+  // a branch, whose result then waits for every load in flight
   double xp[3][EK], xa[3][EK], xb[3][EK], xZ[3];
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
@@ -135,7 +166,9 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
     for (int jj = 0; jj < EK; ++jj) {
       const int m = min(nn[e][jj], Np - 1);
       const double a0 = qn[m], rb = qbl[min(nn[e][jj], Nfp - 1)];
-      xp[e][jj] = inner ? a0 : (hb ? rb : 0.0);
+      const long long bits = (__double_as_longlong(a0) & -(long long)inner) |
+                             (__double_as_longlong(rb) & -(long long)hb);
+      xp[e][jj] = __longlong_as_double(bits);
       xa[e][jj] = qn[Np + m];
       xb[e][jj] = qn[2 * Np + m];
     }
@@ -145,10 +178,6 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
 #pragma unroll
   for (int r = 0; r < RG; ++r) ps[r] = 0.0;
   if (P > 0) {
-    // the old residuals, loaded linearly now and staged after the MFMAs
-    double vr[KL];
-#pragma unroll
-    for (int k = 0; k < KL; ++k) vr[k] = b.res2[wbase + min(lane + 64 * k, cnt - 1)];
     const double* fj = sops + ta;
     const double* fl = sops + 2 * RG * RG * 16 + ta;
     const double Ki = Kb / (1.0 + sg[i]);
@@ -225,9 +254,6 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
         }
       }
     }
-#pragma unroll
-    for (int k = 0; k < KL; ++k)
-      if (lane + 64 * k < cnt) sr[lane + 64 * k] = vr[k];
     // ---- LSRK update of the rows this lane holds, into the stage
 #pragma unroll
     for (int r = 0; r < RG; ++r) {
@@ -268,7 +294,7 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
       const int x = lane + 64 * k;
-      if (x < cnt) {
+      if (64 * k < cnt && x < cnt) {
         b.q2n[wbase + x] = sq[x];
         b.res2[wbase + x] = sr[x];
       }
@@ -287,7 +313,7 @@ __global__ void __launch_bounds__(kWaves2 * 64, 2) k_faces(LvlF F, Lvl2 L2, Face
   __shared__ double sops[D::NFRAG * 16];
   __shared__ double sg[16];
   __shared__ int smask[3 * Nfp];
-  __shared__ double sbuf[kWaves2][2][16 * 3 * Np];  // per wave: q2 and res2 of its pairs
+  __shared__ __attribute__((aligned(16))) char stage[kWaves2 * 2 * D::SB];  // per wave: q2, res2
   fill_lds<kWaves2 * 64, D::NFRAG * 16>(sops, F.ops, threadIdx.x);
   fill_lds<kWaves2 * 64, 3 * Nfp>(smask, L2.fmask, threadIdx.x);
   if (threadIdx.x < L2.P) sg[threadIdx.x] = L2.gamma[threadIdx.x];
@@ -295,7 +321,7 @@ __global__ void __launch_bounds__(kWaves2 * 64, 2) k_faces(LvlF F, Lvl2 L2, Face
   const XcdRange rg_((long long)ngrp * sh.n);
   for (long long it = rg_.lo; it < rg_.hi; it += rg_.step) {
     const int k = (int)(it / ngrp), bx = (int)(it - (long long)k * ngrp);
-    faces_item<N, T3>(F, L2, b, sh, A, B, dt, bx, k, sops, sg, smask, sbuf);
+    faces_item<N, T3>(F, L2, b, sh, A, B, dt, bx, k, sops, sg, smask, stage);
   }
 }
 
