@@ -7,7 +7,9 @@
  *
  * Every function returns dgh_status (0 = DGH_OK).  Nothing aborts, throws or
  * exits; on failure dgh_last_error() holds the reason.  One context per host
- * thread; contexts share no state.
+ * thread; contexts share no state apart from a process-wide, lock-protected
+ * cache of per-device launch limits (LDS sizes, resident workgroups), so
+ * contexts on different devices or threads may step at the same time.
  *
  * Call order: dgh_create -> dgh_upload_mesh -> dgh_set_order -> dgh_set_habc
  * -> dgh_set_material -> dgh_workspace_size -> dgh_bind_workspace ->
