@@ -69,3 +69,69 @@ def rel_errors(got, ref):
         den = nr if nr > 1e-30 * scale else scale
         out[k] = float(np.linalg.norm(got[k] - ref[k]) / den) if den > 0 else 0.0
     return out
+
+
+def corner_block(VX, E, n, m):
+    """The m^3-cell block at the far corner (x, y, z up to the box's upper
+    faces) of the n^3-cell Kuhn mesh ``workloads.kuhn_mesh(n)``: its tets in
+    the full mesh's order with the full mesh's coordinates.  Returns
+    (VXb, Eb, efull, cmin): the block mesh, the full index of each block
+    element and each block element's smallest cell index over the three axes."""
+    i0 = n - m
+    r = np.arange(i0, n)
+    kc, jc, ic = [a.ravel() for a in np.meshgrid(r, r, r, indexing="ij")]
+    cell = (kc * n + jc) * n + ic
+    efull = (cell[:, None] * 6 + np.arange(6)[None, :]).ravel()
+    vids, inv = np.unique(E[efull], return_inverse=True)    # order-preserving renumbering
+    cmin = np.repeat(np.minimum(np.minimum(kc, jc), ic), 6)
+    return VX[vids], inv.reshape(-1, 4).astype(np.int32), efull, cmin
+
+
+def kuhn_triangle_order(VX, E, n):
+    """Canonical triangle index (domain face, tet, local face) -> row of the
+    n^3-cell Kuhn mesh with HABC on all six faces, from the boundary cells."""
+    from oracle.reference import FACE_VERTS
+    fv = np.array(FACE_VERTS)
+    out, base = {}, 0
+    c = np.arange(n ** 3)
+    cidx = [c % n, (c // n) % n, c // (n * n)]
+    for d in range(6):
+        ax, hi = d // 2, d % 2
+        cells = c[cidx[ax] == (n - 1 if hi else 0)]
+        e = (cells[:, None] * 6 + np.arange(6)[None, :]).ravel()
+        x = VX[E[e][:, fv], ax]                                    # (tets, 4 faces, 3)
+        on = np.all(x == (1.0 if hi else 0.0), axis=2)
+        te, tf = np.nonzero(on)
+        recs = sorted(zip(e[te].tolist(), tf.tolist()))
+        for k, (ee, ff) in enumerate(recs):
+            out[(d, ee, ff)] = base + k
+        base += len(recs)
+    return out
+
+
+def block_maps(om, VX, E, n, m, efull):
+    """Full-mesh rows of every block array (the block's oracle mesh om; full
+    mesh with HABC on all faces): tets, triangles, lines (the last m of their
+    domain edge) and the corner x+ y+ z+ (index 7).  Also returns each block
+    line's position along its edge."""
+    tri = kuhn_triangle_order(VX, E, n)
+    tmap = np.array([tri[(int(om.tri_dface[t]), int(efull[om.tri_elem[t]]), int(om.tri_face[t]))]
+                     for t in range(om.Ktri)], dtype=np.int64)
+    first = {int(d): int(np.argmax(om.lin_dedge == d)) for d in np.unique(om.lin_dedge)}
+    lpos = np.array([l - first[int(om.lin_dedge[l])] for l in range(om.Klin)], dtype=np.int64)
+    lmap = om.lin_dedge * n + (n - m) + lpos
+    maps = {"q3": efull, "res3": efull, "q2": tmap, "res2": tmap, "qb3": tmap, "q0_3": tmap,
+            "q1": lmap, "res1": lmap, "qb2": lmap, "q0_2": lmap, "qb1": np.array([7])}
+    return maps, lpos
+
+
+def block_sample(om, cmin, lpos, n, m, cut):
+    """Rows of the block's arrays at least `cut` cells from its cut faces."""
+    far = cmin >= n - m + cut
+    keep = {"q3": far, "res3": far, "qb1": np.ones(1, dtype=bool)}
+    for k in ("q2", "res2", "qb3", "q0_3"):
+        keep[k] = far[om.tri_elem]
+    for k in ("q1", "res1", "qb2", "q0_2"):
+        keep[k] = lpos >= cut
+    return keep
+

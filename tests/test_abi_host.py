@@ -83,6 +83,20 @@ def test_general_mesh_inputs():
     assert np.abs(s.node_coords() - o.node_coords()).max() < 1e-14
 
 
+def test_state_size_limit():
+    """The kernels address a shot's 3D state with 32-bit byte offsets: a
+    70^3 x 6 = 2,058,000-tet mesh fits at N = 5 (3.69 GB per 3D array) and
+    is refused at N = 6 (6.9 GB)."""
+    from paper_1610_05023_amd import Solver, DghError
+    VX, E = w.kuhn_mesh(70)
+    K = E.shape[0]
+    s5 = Solver(VX, E, 5, 0, np.ones(K), np.ones(K))
+    assert s5.workspace_size() > 2 * K * 4 * 56 * 8
+    s6 = Solver(VX, E, 6, 0, np.ones(K), np.ones(K))
+    with pytest.raises(DghError, match="4 GiB"):
+        s6.workspace_size()
+
+
 def test_kuhn_counts():
     from paper_1610_05023_amd import Solver
     n = 5

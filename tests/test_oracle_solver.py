@@ -192,3 +192,49 @@ def test_habc_reflection_decreases_with_order():
     ref = run(0, True)[big]
     err = [np.linalg.norm(run(P, False) - ref) / np.linalg.norm(ref) for P in (0, 1, 3)]
     assert err[0] > 5 * err[1] and err[1] > 2 * err[2], err
+
+
+def test_far_corner_block_reproduces_full_mesh():
+    """The sampling used on meshes too large for the oracle: one step on the
+    m^3-cell block at the far corner (its other faces cut, basic ABC) equals
+    one step on the whole n^3-cell mesh at least six cells from the cuts, in
+    every array of every level (one step moves information at most five
+    element layers).  Also checks the full mesh's canonical triangle order
+    rebuilt from its boundary cells."""
+    from parity_util import ARRAYS, block_maps, block_sample, corner_block, kuhn_triangle_order
+    n, m, cut, N, P = 14, 12, 6, 3, 2
+    h = 1.0 / n
+    VX, E = w.kuhn_mesh(n)
+    K = E.shape[0]
+    full = Oracle(VX, E, N, P, np.ones(K), np.ones(K))
+    fm = full.m
+    tri = kuhn_triangle_order(VX, E, n)
+    assert len(tri) == fm.Ktri
+    for t in range(fm.Ktri):
+        assert tri[(int(fm.tri_dface[t]), int(fm.tri_elem[t]), int(fm.tri_face[t]))] == t
+    VXb, Eb, efull, cmin = corner_block(VX, E, n, m)
+    blk = Oracle(VXb, Eb, N, P, np.ones(len(Eb)), np.ones(len(Eb)),
+                 face_bc=("abc", "habc", "abc", "habc", "abc", "habc"))
+    maps, lpos = block_maps(blk.m, VX, E, n, m, efull)
+    # the maps point at the same places: nodes, triangle and line positions
+    assert np.array_equal(blk.node_coords(), full.node_coords()[efull])
+    assert np.array_equal(blk.m.tri_xn, fm.tri_xn[maps["q2"]])
+    assert np.array_equal(blk.m.lin_xn, fm.lin_xn[maps["q1"]])
+    shapes = full.shapes()
+    full.s = {k: w.random_array(shapes[k], 50 + j) for j, k in enumerate(ARRAYS)}
+    blk.s = {k: full.s[k][maps[k]].copy() for k in ARRAYS}
+    xs = (1 - 3.3 * h, 1 - 4.2 * h, 1 - 2.1 * h)
+    full.set_source(xs, 6.0, 0.0)
+    blk.set_source(xs, 6.0, 0.0)
+    dt = w.kuhn_dt(n, N, 1.0)
+    full.step(1, dt)
+    blk.step(1, dt)
+    keep = block_sample(blk.m, cmin, lpos, n, m, cut)
+    for k in ARRAYS:
+        a, b = blk.s[k][keep[k]], full.s[k][maps[k]][keep[k]]
+        assert a.size > 0, k
+        assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b), k
+    # and the cut does matter nearer than that
+    near = ~keep["q3"]
+    a, b = blk.s["q3"][near], full.s["q3"][maps["q3"]][near]
+    assert np.linalg.norm(a - b) > 1e-6 * np.linalg.norm(b)
