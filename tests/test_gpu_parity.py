@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 import workloads as w
-from parity_util import make_case, make_solver, run_oracle, rel_errors
+from parity_util import (ARRAYS, block_maps, block_sample, corner_block, make_case,
+                         make_solver, rel_errors, run_oracle)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -117,6 +118,55 @@ def test_general_mesh_random_medium(n):
                 state=state, source=((0.43, 0.55, 0.47), 4.0, 0.1),
                 box=np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0]))
     _check(case, 30, 0.5 * w.kuhn_dt(n, N, 3.0))
+
+
+def test_largest_mesh_far_corner_against_oracle():
+    """The largest Kuhn mesh whose 3D state a shot can hold at N = 5:
+    70^3 x 6 = 2,058,000 tets, 3.69 GB per 3D array, so byte offsets run up
+    to just below 2^32. HABC P = 2 on all faces, a random state in every
+    array, and a source near the far corner. After one GPU step, every array
+    of the 16^3-cell block at the far corner (x, y, z up to 1: the highest
+    element slots and offsets, three HABC faces, three edges and a corner) is
+    checked against the oracle run on that block alone. The block's other
+    faces are cut faces (basic ABC). One step moves information at most five
+    element layers, so at least six cells from the cut faces the two runs
+    agree to round-off."""
+    from oracle.solver import Oracle
+    from paper_1610_05023_amd import Solver
+    n, m, cut, N, P = 70, 16, 6, 5, 2
+    h = 1.0 / n
+    VX, E = w.kuhn_mesh(n)
+    K = E.shape[0]
+    VXb, Eb, efull, cmin = corner_block(VX, E, n, m)
+    fb_block = ("abc", "habc", "abc", "habc", "abc", "habc")
+    o = Oracle(VXb, Eb, N, P, np.ones(len(Eb)), np.ones(len(Eb)), face_bc=fb_block,
+               periodic=(False,) * 3)
+    om = o.m
+    maps, lpos = block_maps(om, VX, E, n, m, efull)
+    print(f"[max] block: {len(Eb)} tets, {om.Ktri} triangles, {om.Klin} lines, "
+          f"{om.Kpnt} corner", flush=True)
+    s = Solver(VX, E, N, P, np.ones(K), np.ones(K)).bind()
+    full_shapes = s.shapes()
+    state = {k: w.random_array(full_shapes[k], 90 + j) for j, k in enumerate(ARRAYS)}
+    o.s = {k: state[k][maps[k]].copy() for k in ARRAYS}
+    s.set_state(state)
+    del state
+    xs = (1 - 3.3 * h, 1 - 4.2 * h, 1 - 2.1 * h)
+    s.set_source(xs, 6.0, 0.0)
+    o.set_source(xs, 6.0, 0.0)
+    dt = w.kuhn_dt(n, N, 1.0)
+    print(f"[max] {K} tets, workspace {s.workspace_size() / 2**30:.1f} GiB: one step", flush=True)
+    s.step(1, dt)
+    got = s.read_fields()
+    s.close()
+    o.step(1, dt)
+    keep = block_sample(om, cmin, lpos, n, m, cut)
+    err = {}
+    for k in ARRAYS:
+        a, b = got[k][maps[k]][keep[k]], o.s[k][keep[k]]
+        err[k] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    print("[max] errors", {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
+    assert all(v <= TOL for v in err.values()), err
 
 
 def test_contexts_in_two_threads():
