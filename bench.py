@@ -208,8 +208,8 @@ def main():
                     help="run 1 GiB reference kernels first (for PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not run.", file=sys.stderr)
+        print(f"bench.py: the step runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -16,10 +16,11 @@ Contents
   solver     the multidimensional explicit step (Algorithm 1) with the DG
              right-hand sides (Section 3.2) and the five-stage low-storage
              Runge-Kutta scheme; energy
-  mlp        the small boundary-closure network (forward/backward), FP64
+  closure    the small boundary-closure network (forward, gradient), FP64;
+             not part of the paper
 
-Every function cites the passage it follows.  Readings of garbled or silent
-passages are listed in the design doc (characteristics carry a factor 1/2, the 2D
-and 1D fluxes use Z = rho*c of the boundary cell, the edge system signs follow
-the scalar equations of the procedure).
+Every function cites the passage it follows.  Where the paper is silent or
+garbled the oracle takes these readings: characteristics carry a factor 1/2,
+the 2D and 1D fluxes use Z = rho*c of the boundary cell, and the signs of the
+edge and corner systems follow the scalar equations of the procedure.
 """
