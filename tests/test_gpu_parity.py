@@ -96,7 +96,8 @@ def test_mixed_faces_random():
     _check(case, 20, 1e-3)
 
 
-@pytest.mark.parametrize("n,N,precision", [(3, 3, 0), (4, 3, 0), (4, 3, 2), (3, 5, 0), (3, 5, 2)])
+@pytest.mark.parametrize("n,N,precision", [(3, 3, 0), (4, 3, 0), (4, 3, 2), (3, 5, 0), (3, 5, 2),
+                                           (3, 1, 0), (3, 6, 0), (3, 2, 2), (3, 6, 2)])
 def test_general_mesh_random_medium(n, N, precision):
     """An unstructured mesh (n^3 Kuhn cells with the interior vertices moved
     by up to 0.1 h, the elements shuffled, each element's vertices rotated;
@@ -104,8 +105,8 @@ def test_general_mesh_random_medium(n, N, precision):
     takes the general element order, and the interior faces meet at every
     vertex permutation.  HABC P = 3 on all faces, random state, a source,
     30 steps at half the Kuhn time step of the fastest medium.  n = 3 gives
-    162 elements, so the last tile of the layout is ragged.  N = 3 runs the
-    tile-on-chip 3D kernels, N = 5 the register-streaming ones.  The FP32
+    162 elements, so the last tile of the layout is ragged.  N <= 4 runs the
+    tile-on-chip 3D kernels, N = 5, 6 the register-streaming ones.  The FP32
     variant (precision 2) is held to 1e-4, the guard of its rounding error
     on the Kuhn mesh."""
     from oracle.solver import Oracle
