@@ -975,7 +975,8 @@ extern "C" {
 dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
   if (!c) return DGH_EINVAL;
   if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "step before bind");
-  if (n_steps < 0 || !(dt > 0) || !std::isfinite(t_start)) return fail(c, DGH_EINVAL, "bad step arguments");
+  if (n_steps < 0 || !(dt > 0) || !std::isfinite(dt) || !std::isfinite(t_start))
+    return fail(c, DGH_EINVAL, "bad step arguments");
   if (n_steps == 0) return DGH_OK;
   if (c->graph && !c->timing) {
     if (!c->gx[0] || c->gdt != dt || c->gclosure != c->closure || c->grecord != c->record) {
@@ -1098,7 +1099,8 @@ dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, d
       return fail(c0, DGH_EINVAL, "group members need the same N, precision, device and stream");
     if (c->closure || c->record) return fail(c0, DGH_EINVAL, "group steps run the plain method");
   }
-  if (n_steps < 0 || !(dt > 0) || !std::isfinite(t_start)) return fail(c0, DGH_EINVAL, "bad step arguments");
+  if (n_steps < 0 || !(dt > 0) || !std::isfinite(dt) || !std::isfinite(t_start))
+    return fail(c0, DGH_EINVAL, "bad step arguments");
   if (n_steps == 0) return DGH_OK;
   hipStream_t st = c0->stream;
   // member tables for both parities of the double buffers; the previous
@@ -1108,6 +1110,8 @@ dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, d
   for (int i = 0; i < n; ++i) {
     dgh_ctx* c = ctxs[i];
     const Layout& L = c->lay;
+    // work items of 4 tiles: one per wave of the tile-on-chip kernels'
+    // workgroups (4 waves in both the FP64 and the FP32 kernel)
     const int ngrp = (c->ntile + 3) / 4;
     for (int p = 0; p < 2; ++p) {
       const int o = c->cur ^ p;

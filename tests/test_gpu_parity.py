@@ -231,7 +231,10 @@ def test_deterministic_rerun():
 def test_check_finite_and_energy():
     """The failure check: clean state passes with its own energy as the
     reference; a smaller reference reports growth; a NaN planted in a
-    boundary-level array (host input, valid for every kernel) is found."""
+    boundary-level array (host input, valid for every kernel) is found; a
+    step with a time step that is not finite and positive is refused before
+    any launch."""
+    from paper_1610_05023_amd.binding import DghError
     case = make_case(n=4, N=3, P=3, init="random", seed=61)
     s = make_solver(case)
     st, e = s.check()
@@ -245,6 +248,9 @@ def test_check_finite_and_energy():
         s.set_state(bad)
         assert s.check()[0] == "DGH_ENONFINITE", name
     s.set_state(case["state"])
+    for bad_dt in (0.0, -1e-3, float("inf"), float("nan")):
+        with pytest.raises(DghError):
+            s.step(1, bad_dt)
     s.step(5, 1e-3)
     assert s.check()[0] == "DGH_OK"
 
