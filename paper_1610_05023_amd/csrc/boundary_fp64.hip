@@ -120,6 +120,23 @@ __global__ void __launch_bounds__(512, 4) k_boundary(Lvl2 L2, Lvl1 L1, int np3, 
                  Z = L1.geo[l * 4 + 3];
     int info[8];
     for (int k = 0; k < 8; ++k) info[k] = L1.info[l * 8 + k];
+    // this thread's entry (row, node) of the 2P x Np table of outgoing 2D
+    // characteristics: the new face traces (written by the face kernel,
+    // never by this one) are loaded now, in flight with the loads below
+    // (2P Np <= 168 < 512 threads: one entry per thread)
+    const bool yon = tid < n2 * Np;
+    double ypv = 0.0, yuv = 0.0, yzt = 1.0;
+    if (yon) {
+      const int row = tid / Np, cy = tid - row * Np;
+      const int side = row / P, ii = row - side * P;
+      const int t = info[side], comp = info[2 + side];
+      const int node = L1.trinode[((size_t)l * 2 + side) * Np + cy];
+      const double* q = b.q2n + ((size_t)t * P + ii) * 3 * L2.Np;
+      const int cc = comp > 0 ? comp : -comp;
+      yzt = L2.geo[(size_t)t * 8 + 6];
+      ypv = q[node];
+      yuv = q[cc * L2.Np + node];
+    }
     // loads of this thread's nodes (x = tid + h nth, h < NPT: NPT nth >=
     // P^2 Np1): old residuals, q0 of both faces, and the exterior values at
     // both line ends (neighbour line or corner r-)
@@ -195,24 +212,18 @@ __global__ void __launch_bounds__(512, 4) k_boundary(Lvl2 L2, Lvl1 L1, int np3, 
       sw[s * Np + a] = wn;
     }
     __syncthreads();
-    // outgoing 2D characteristics (new 2D traces, written by this block) and b
-    for (int y = tid; y < n2 * Np; y += nth) {
-      const int row = y / Np, c = y - row * Np;
+    // outgoing 2D characteristics (from the new 2D traces loaded above) and b
+    if (yon) {
+      const int row = tid / Np, c = tid - row * Np;
       const int side = row / P, ii = row - side * P;
-      const int t = info[side], comp = info[2 + side];
-      const int node = L1.trinode[((size_t)l * 2 + side) * Np + c];
-      const double* q = b.q2n + ((size_t)t * P + ii) * 3 * L2.Np;
-      const double sgn = comp > 0 ? 1.0 : -1.0;
-      const int cc = comp > 0 ? comp : -comp;
-      const double zt = L2.geo[(size_t)t * 8 + 6];
-      const double pv = q[node], uv = q[cc * L2.Np + node];
+      const double sgn = info[2 + side] > 0 ? 1.0 : -1.0;
       double bb = 0.0;
       if (side == 0)
         for (int jj = 0; jj < P; ++jj) bb += cg[jj] * sps[(ii * P + jj) * Np + c];
       else
         for (int i2 = 0; i2 < P; ++i2) bb += cg[i2] * sps[(i2 * P + ii) * Np + c];
       sb[row * Np + c] = bb * L1.invM;
-      srp[row * Np + c] = 0.5 * (pv + zt * sgn * uv);
+      srp[row * Np + c] = 0.5 * (ypv + yzt * sgn * yuv);
     }
     __syncthreads();
     // edge system r- = G r+ + H b
@@ -298,7 +309,9 @@ hipError_t launch_boundary(const Lvl2& L2, const Lvl1& L1, const Lvl0& L0,
   const size_t a1 = Np1 * Np1 + 2 * Np1 + 2 * n2 * n2 + 2 * PP + P + PP * 2 * Np1 +
                     2 * PP * Np1 + 3 * n2 * Np1;
   Bufs b{q2o, q2n, res2, qb2, qb3, q03, q3n, q1o, q1n, res1, qb1, q02};
-  if (PP * Np1 > 1024) return hipErrorInvalidValue;
+  // edge nodes at most two per thread; the 2P x Np1 table of outgoing 2D
+  // characteristics one entry per thread
+  if (PP * Np1 > 1024 || n2 * Np1 > 512) return hipErrorInvalidValue;
   const size_t lds = sizeof(double) * a1;
   // one edge node per thread unless P^2 Np1 exceeds the block (P > 10)
   if (PP * Np1 <= 512) {

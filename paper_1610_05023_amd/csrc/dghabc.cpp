@@ -722,10 +722,11 @@ dgh_status dgh_set_state(dgh_ctx* c, int shot, const double* const* arr) {
   const int Np = m.tet.Np;
   const int cur = c->cur;
   std::vector<double> buf((size_t)c->ntile * 4 * Np * dgh::kTile);
-  std::vector<double> zero((size_t)m.K * 4 * Np, 0.0);
   for (int which : {DGH_Q3, DGH_RES3}) {
-    const double* src = (arr && arr[which]) ? arr[which] : zero.data();
-    to_tiles(src, buf.data(), c->slot2elem, Np);
+    if (arr && arr[which])
+      to_tiles(arr[which], buf.data(), c->slot2elem, Np);
+    else
+      std::fill(buf.begin(), buf.end(), 0.0);   // a missing array is zero
     const Region& r = which == DGH_Q3 ? L.q3[cur] : L.res3;
     char* dst = c->ws + r.off + shot * L.st3 * L.e3;
     if (L.e3 == 4) {   // FP32 state: rounded on upload
