@@ -35,7 +35,7 @@ struct Region {
 struct Layout {
   size_t total = 0;
   Region q3[2], res3, geo3, zn3, nbr3, ops3, ops3f, fmask3, fmap3, mass3, J3, esum;
-  Region q2[2], res2, qb3, q03, geo2, info2, tetnode2, nbrnode2, ops2, fmask2, gamma;
+  Region q2[2], res2, qb3, q03, geo2, edge2, info2, tetnode2, nbrnode2, ops2, fmask2, gamma;
   Region q1[2], res1, qb2, q02, geo1, info1, trinode1, ops1, cji, cij, G, H;
   Region qb1, info0, nrm0, T, srcw, srcp, flags, ops2f;
   Region mlpw, hist, csamp;   // learned closure: parameters, trace history, samples
@@ -124,7 +124,7 @@ struct HostArrays {
   std::vector<double> geo3, zn3, ops3, mass3, J3, ops2f;
   std::vector<float> ops3f;
   std::vector<int> nbr3, fmask3, fmap3;
-  std::vector<double> geo2, ops2;
+  std::vector<double> geo2, edge2, ops2;
   std::vector<int> info2, tetnode2, nbrnode2, fmask2;
   std::vector<double> geo1, ops1;
   std::vector<int> info1, trinode1;
@@ -281,6 +281,35 @@ void build_host_arrays(dgh_ctx* c, HostArrays& h) {
       h.info2[t * 8 + 3 + f] = code;
     }
   }
+  // per edge of each triangle (edges s = -1, r + s = 0, r = -1, whose
+  // n fsc are -grad s, grad(r + s), -grad r): the unit in-plane normal, the
+  // face scale, and the weights of the upwind flux against the exterior
+  // state, whose impedance is the neighbour triangle's across an inner edge
+  // and the own one on the boundary of the face
+  h.edge2.assign((size_t)Kt * 24, 0.0);
+  for (int t = 0; t < Kt; ++t) {
+    const double rx = h.geo2[t * 8], ry = h.geo2[t * 8 + 1], sx = h.geo2[t * 8 + 2],
+                 sy = h.geo2[t * 8 + 3], Z = h.geo2[t * 8 + 6];
+    for (int f = 0; f < 3; ++f) {
+      const double cr = f == 0 ? 0.0 : (f == 1 ? 1.0 : -1.0);
+      const double cs = f == 2 ? 0.0 : (f == 1 ? 1.0 : -1.0);
+      double na = cr * rx + cs * sx, nb = cr * ry + cs * sy;
+      const double fsc = std::sqrt(na * na + nb * nb);
+      na /= fsc;
+      nb /= fsc;
+      const int code = h.info2[t * 8 + 3 + f];
+      const double ZP = code >= 0 ? h.geo2[(size_t)code * 8 + 6] : Z;
+      const double iZ = 1.0 / (Z + ZP);
+      double* o = &h.edge2[((size_t)t * 3 + f) * 8];
+      o[0] = na;
+      o[1] = nb;
+      o[2] = fsc;
+      o[3] = ZP * iZ;        // aM
+      o[4] = Z * iZ;         // aP
+      o[5] = iZ;
+      o[6] = Z * (ZP * iZ);  // bZ
+    }
+  }
   {
     // MFMA A-fragments of the face kernel (see LvlF::ops)
     const int RG = (Np2 + 3) / 4, EK = (Nfp2 + 3) / 4;
@@ -398,6 +427,7 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.qb3, S * L.stb3 * d);
   L.add(L.q03, S * L.stb3 * d);
   L.add(L.geo2, (size_t)std::max(1, Kt * 8) * d);
+  L.add(L.edge2, (size_t)std::max(1, Kt * 24) * d);
   L.add(L.info2, (size_t)std::max(1, Kt * 8) * i4);
   L.add(L.tetnode2, (size_t)std::max(1, Kt * Np2) * i4);
   L.add(L.nbrnode2, (size_t)std::max(1, Kt * 3 * Nfp2) * i4);
@@ -467,6 +497,7 @@ void fill_levels(dgh_ctx* c) {
   b.ops = dptr<double>(c, L.ops2);
   b.fmask = dptr<int>(c, L.fmask2);
   b.geo = dptr<double>(c, L.geo2);
+  b.edge = dptr<double>(c, L.edge2);
   b.info = dptr<int>(c, L.info2);
   b.tetnode = dptr<int>(c, L.tetnode2);
   b.nbrnode = dptr<int>(c, L.nbrnode2);
@@ -677,6 +708,7 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
   HIPCHECK(c, upload(c, L.mass3, h.mass3));
   HIPCHECK(c, upload(c, L.J3, h.J3));
   HIPCHECK(c, upload(c, L.geo2, h.geo2));
+  HIPCHECK(c, upload(c, L.edge2, h.edge2));
   HIPCHECK(c, upload(c, L.info2, h.info2));
   HIPCHECK(c, upload(c, L.tetnode2, h.tetnode2));
   HIPCHECK(c, upload(c, L.nbrnode2, h.nbrnode2));

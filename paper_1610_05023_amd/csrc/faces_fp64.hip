@@ -40,6 +40,8 @@ struct Dims2 {
   // bytes of one LDS copy of a span (q2 or res2): whole 1 KB chunks of the
   // direct loads, with room for a span starting 8 bytes past a 16-byte boundary
   static constexpr int SB = ((SPAN + 1) * 8 + 1023) / 1024 * 1024;
+  static constexpr int EB = 16 * 24 * 8;     // edge constants of at most 16 triangles
+  static constexpr int STAGE = 2 * SB + EB;  // per wave: q2, res2, edge constants
 };
 
 typedef __attribute__((address_space(3))) void* lds_ptr;
@@ -88,8 +90,9 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
   // wave's LDS stage by direct buffer-to-LDS loads (16 bytes per lane from
   // the 16-byte boundary at or before the span; the descriptors end with the
   // span) and, at the end, stored back with linear (coalesced) stores
-  char* stq = stage + (size_t)wv * 2 * D::SB;
+  char* stq = stage + (size_t)wv * D::STAGE;
   char* str = stq + D::SB;
+  char* ste = str + D::SB;
   const int cnt = ntw * P * 3 * Np;
   const size_t wbase = (size_t)w0 * P * 3 * Np;
   const int shq = (int)((reinterpret_cast<size_t>(b.q2o + wbase) >> 3) & 1);
@@ -109,6 +112,13 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
       __builtin_amdgcn_raw_ptr_buffer_load_lds(Rr, (lds_ptr)(str + c * 1024), 16, lane * 16,
                                                c * 1024, 0, 0);
     }
+    // the edge constants of the wave's triangles (192 bytes each, 16-byte
+    // aligned), shared by every shot
+    const unsigned be = (unsigned)ntw * 24 * 8;
+    const Rsrc Re = span_rsrc(L2.edge + (size_t)w0 * 24, be);
+    for (int c = 0; c < (int)((be + 1023) >> 10); ++c)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(Re, (lds_ptr)(ste + c * 1024), 16, lane * 16,
+                                               c * 1024, 0, 0);
   }
   // ---- every other load that depends on the triangle only
   const double* gg = L2.geo + (size_t)t * 8;
@@ -151,7 +161,7 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
   // triangle, line 0 of qb2) and the values are selected afterwards by bit
   // masks: a select on a loaded value lets the compiler move the load into
   // a branch, whose result then waits for every load in flight
-  double xp[3][EK], xa[3][EK], xb[3][EK], xZ[3];
+  double xp[3][EK], xa[3][EK], xb[3][EK];
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     const bool inner = code[e] >= 0;
@@ -159,7 +169,6 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
     const bool hb = !inner && (c & 3) == 0;
     const int tn = inner ? code[e] : t;
     const int lq = hb ? (c >> 3) : 0, sd = hb ? ((c >> 2) & 1) : 0;
-    xZ[e] = L2.geo[(size_t)tn * 8 + 6];
     const double* qn = b.q2o + (P > 0 ? ((size_t)tn * P + i) * 3 * Np : 0);
     const double* qbl = b.qb2 + (((size_t)lq * 2 + sd) * Pc + ic) * Nfp;
 #pragma unroll
@@ -216,18 +225,13 @@ __device__ __forceinline__ void faces_item(const LvlF& F, const Lvl2& L2, FaceBu
     // (Gs for edge 0, -Gr and -Gs for edge 1, Gr for edge 2).
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-      const double cr = e == 0 ? 0.0 : (e == 1 ? 1.0 : -1.0);
-      const double cs = e == 2 ? 0.0 : (e == 1 ? 1.0 : -1.0);
-      double na = cr * rx + cs * sx, nb = cr * ry + cs * sy;
-      const double fsc = sqrt(na * na + nb * nb);
-      na /= fsc;
-      nb /= fsc;
+      // unit normal, face scale and flux weights of this edge (host-built)
+      const double* ec = reinterpret_cast<const double*>(ste) + (t - w0) * 24 + e * 8;
+      const double na = ec[0], nb = ec[1], fsc = ec[2];
+      const double aM = ec[3], aP = ec[4], iZ = ec[5], bZ = ec[6], cP = fsc * Ki;
       const bool inner = code[e] >= 0;
       const int c = -1 - code[e];
       const bool hb = !inner && (c & 3) == 0, dir = !inner && (c & 3) == 2;
-      const double ZP = inner ? xZ[e] : Z;
-      const double iZ = 1.0 / (Z + ZP);
-      const double aM = ZP * iZ, aP = Z * iZ, bZ = Z * aM, cP = fsc * Ki;
 #pragma unroll
       for (int jj = 0; jj < EK; ++jj) {
         const int kc = min(4 * jj + g, Nfp - 1);   // rows beyond Nfp: LIFT columns are 0
@@ -313,7 +317,7 @@ __global__ void __launch_bounds__(kWaves2 * 64, 2) k_faces(LvlF F, Lvl2 L2, Face
   __shared__ double sops[D::NFRAG * 16];
   __shared__ double sg[16];
   __shared__ int smask[3 * Nfp];
-  __shared__ __attribute__((aligned(16))) char stage[kWaves2 * 2 * D::SB];  // per wave: q2, res2
+  __shared__ __attribute__((aligned(16))) char stage[kWaves2 * D::STAGE];
   fill_lds<kWaves2 * 64, D::NFRAG * 16>(sops, F.ops, threadIdx.x);
   fill_lds<kWaves2 * 64, 3 * Nfp>(smask, L2.fmask, threadIdx.x);
   if (threadIdx.x < L2.P) sg[threadIdx.x] = L2.gamma[threadIdx.x];

@@ -63,6 +63,9 @@ struct Lvl2 {
   const double* ops;   // Dr2 | Ds2 | LIFT2 (Np x 3Nfp)
   const int* fmask;    // 3 x Nfp
   const double* geo;
+  // [Ktri][3 edges][8]: unit in-plane normal (2), face scale, upwind-flux
+  // weights aM = ZP/(Z+ZP), aP = Z/(Z+ZP), iZ = 1/(Z+ZP), bZ = Z aM, pad
+  const double* edge;
   const int* info;
   const int* tetnode;  // [Ktri][Np2] node of the owning tet
   const int* nbrnode;
