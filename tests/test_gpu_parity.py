@@ -74,6 +74,44 @@ def test_wave_through_faces_edges_corners():
     assert np.abs(ref["qb1"]).max() > 1e-8
 
 
+@pytest.mark.parametrize("name,precision", [("1b", 0), ("3", 0), ("3", 2)])
+def test_thousand_steps_against_stored_oracle(name, precision):
+    """1000 steps of the 8^3 x 6 Gaussian case with HABC P = 3 on all faces,
+    at N = 3 (config 1b) and N = 5 (the precision case), against the
+    oracle's run stored in tests/golden/long_runs.json. That file is written
+    by make_long_runs.py from the oracle alone and holds, per array, the l2
+    norm and 128 evenly spaced values. By step 1000 the pulse has crossed the
+    faces, edges and corners and mostly left the domain, so differences are
+    measured on the scale of the initial field, which sets the round-off:
+    pointwise against the initial peak, norms against the initial q3 norm.
+    The bounds are 1e-11 in FP64 and 1e-4 for the FP32 variant."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "long_runs.json")) as f:
+        g = json.load(f)[name]
+    cfg = w.config(name)
+    assert (g["n"], g["N"], g["P"], g["steps"]) == (cfg.n, cfg.N, cfg.P, cfg.steps)
+    case = make_case(n=cfg.n, N=cfg.N, P=cfg.P, width=cfg.extra["width"])
+    q0 = g["q3_initial_norm"]
+    assert abs(float(np.linalg.norm(case["state"]["q3"])) - q0) <= 1e-14 * q0
+    peak = float(np.abs(case["state"]["q3"]).max())
+    s = make_solver(case, precision=precision)
+    s.step(cfg.steps, cfg.dt)
+    got = s.read_fields()
+    worst = {}
+    for k, rec in g["arrays"].items():
+        a = got[k].reshape(-1)
+        assert a.size == rec["size"], k
+        d_pt = float(np.abs(a[np.array(rec["index"])] - np.array(rec["values"])).max())
+        d_nm = abs(float(np.linalg.norm(a)) - rec["norm"])
+        worst[k] = max(d_pt / peak, d_nm / q0)
+    print(f"[long] config {name} precision {precision}: q3 norm {g['arrays']['q3']['norm']:.3e} "
+          f"(initial {q0:.3e}); differences", {k: f"{v:.1e}" for k, v in worst.items()},
+          flush=True)
+    tol = 1e-11 if precision == 0 else 1e-4
+    assert all(v <= tol for v in worst.values()), worst
+
+
 def test_layered_medium_with_source():
     """Five random layers (seed 2) on 8^3 x 6 tets, N = 3, P = 3, Ricker
     source off the centre: heterogeneous upwind fluxes and the source term."""

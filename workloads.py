@@ -197,7 +197,13 @@ def config(name):
     centred Gaussian of width 0.05, 100 steps); '1b': same, 1000 steps (the
     wave reaches faces, edges and corners); '1c': same mesh, every state array
     random (seed 11), 100 steps; '2': 40^3 x 6 tets, N=4, P=6, five random
-    layers, Ricker point source near the centre, 1000 steps."""
+    layers, Ricker point source near the centre, 1000 steps; '3': the
+    precision case, config 1's mesh and pulse at N=5, 1000 steps."""
+    if name == "3":
+        n, N, P = 8, 5, 3
+        return Workload(name=name, n=n, N=N, P=P, steps=1000, dt=kuhn_dt(n, N, 1.0),
+                        init="gaussian", seed=0,
+                        extra={"center": (0.5, 0.5, 0.5), "width": 0.05})
     if name in ("1", "1b", "1c"):
         n, N, P = 8, 3, 3
         dt = kuhn_dt(n, N, 1.0)
