@@ -148,6 +148,67 @@ def run_uneven(args):
     print(json.dumps(out))
 
 
+def run_reflection(args):
+    """Accuracy of the absorbing boundary at full size.  The 40^3 x 6-tet
+    layered case with its Ricker source is run with HABC P = 6 and with the
+    basic ABC (P = 0).  The reference is the doubled domain [-0.5, 1.5]^3
+    (80^3 x 6 tets, the same cell size, layers extended sideways and the
+    bottom and top layers downwards and upwards, HABC P = 6).  All three are
+    stepped to t = 0.45.  The waves reach the unit cube's faces from
+    t = 0.17; what the reference's own boundary reflects cannot come back
+    into the unit cube before t = 0.5.  Reports the relative l2 error of q3
+    over the unit cube."""
+    import numpy as np
+    import torch
+    import workloads as w
+    from paper_1610_05023_amd import Solver
+    cfg = w.config("2")
+    n, N, dt = cfg.n, cfg.N, cfg.dt
+    steps = int(round(0.45 / dt))
+    _, _, cuts, cvals, rvals = w.layered_medium(n, seed=2)
+
+    def medium(m, shift):
+        k = (np.arange(6 * m ** 3) // 6) // (m * m)          # cell layer of each element
+        layer = np.searchsorted(cuts, np.clip(k - shift, 0, n - 1), side="right")
+        return rvals[layer].copy(), cvals[layer].copy()
+
+    def run(VX, E, rho, c, P, label):
+        t0 = time.perf_counter()
+        s = Solver(VX, E, N, P, rho, c).bind()
+        s.set_source(cfg.source, cfg.f0, cfg.t0)
+        done = 0
+        while done < steps:
+            k = min(1000, steps - done)
+            s.step(k, dt, done * dt)
+            done += k
+            torch.cuda.synchronize()
+            print(f"[bench] reflection {label}: {done}/{steps} steps, "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        q3 = s.read_fields(["q3"])["q3"]
+        s.close()
+        return q3
+
+    VX, E = w.kuhn_mesh(n)
+    rho, c = medium(n, 0)
+    inner = {P: run(VX, E, rho, c, P, f"P={P}") for P in (6, 0)}
+    m = 2 * n
+    VXo, Eo = w.kuhn_mesh(m, lo=(-0.5,) * 3, hi=(1.5,) * 3)
+    rho_o, c_o = medium(m, n // 2)
+    ref = run(VXo, Eo, rho_o, c_o, 6, "reference")
+    e = np.arange(6 * n ** 3)
+    cell, t = e // 6, e % 6
+    i, j, k = cell % n, (cell // n) % n, cell // (n * n)
+    eo = (((k + n // 2) * m + (j + n // 2)) * m + (i + n // 2)) * 6 + t
+    r = ref[eo]
+    err = {f"P={P}": float(np.linalg.norm(q - r) / np.linalg.norm(r)) for P, q in inner.items()}
+    print(json.dumps({"workload": "reflection: 40^3 x 6 layered case with its Ricker source "
+                                  "against the doubled domain [-0.5, 1.5]^3 (80^3 x 6 tets, "
+                                  "HABC P=6), t = 0.45",
+                      "steps": steps, "dt": dt,
+                      "relative_l2_error_q3_unit_cube": err,
+                      "reference_q3_norm": float(np.linalg.norm(r))}))
+
+
 def cpu_baseline(seconds_target=20.0):
     """The FP64 oracle (numpy, as is) on a bounded sample of the workload:
     the same medium recipe, degree and HABC order on a 20^3 x 6 = 48,000-tet
@@ -189,7 +250,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=40)
-    ap.add_argument("--workload", choices=["layered", "batch", "uneven"], default="layered",
+    ap.add_argument("--workload", choices=["layered", "batch", "uneven", "reflection"],
+                    default="layered",
                     help="layered: the 40^3 layered-medium step (default); batch: 64 shots "
                          "on a 20^3 mesh stepped together")
     ap.add_argument("--shots", type=int, default=64)
@@ -226,6 +288,8 @@ def main():
         torch.cuda.synchronize()
         print("[bench] calibration: 1 GiB fill, 2 x (1 GiB read + 1 GiB write)", file=sys.stderr)
         del x, y
+    if args.workload == "reflection":
+        return run_reflection(args)
     if args.workload == "uneven":
         run_uneven(args)
         return
