@@ -157,7 +157,11 @@ def run_reflection(args):
     stepped to t = 0.45.  The waves reach the unit cube's faces from
     t = 0.17; what the reference's own boundary reflects cannot come back
     into the unit cube before t = 0.5.  Reports the relative l2 error of q3
-    over the unit cube."""
+    over the unit cube.  With --closure the learned closure is trained first
+    (the small recipe of its test: six P = 6 teacher runs of a Gaussian
+    pulse on 8^3 x 6 tets, here at this case's N and time step, so that the
+    network's history of step ends spans the same time as in use) and
+    evaluated on the same case with P = 0."""
     import numpy as np
     import torch
     import workloads as w
@@ -172,9 +176,11 @@ def run_reflection(args):
         layer = np.searchsorted(cuts, np.clip(k - shift, 0, n - 1), side="right")
         return rvals[layer].copy(), cvals[layer].copy()
 
-    def run(VX, E, rho, c, P, label):
+    def run(VX, E, rho, c, P, label, closure=None):
         t0 = time.perf_counter()
         s = Solver(VX, E, N, P, rho, c).bind()
+        if closure is not None:
+            s.set_closure(closure)
         s.set_source(cfg.source, cfg.f0, cfg.t0)
         done = 0
         while done < steps:
@@ -190,7 +196,25 @@ def run_reflection(args):
 
     VX, E = w.kuhn_mesh(n)
     rho, c = medium(n, 0)
-    inner = {P: run(VX, E, rho, c, P, f"P={P}") for P in (6, 0)}
+    inner = {f"P={P}": run(VX, E, rho, c, P, f"P={P}") for P in (6, 0)}
+    if args.closure:
+        from paper_1610_05023_amd.closure import teacher_samples, train
+        nt = 8
+        VXt, Et = w.kuhn_mesh(nt)
+        Kt = Et.shape[0]
+        dt_small = w.kuhn_dt(nt, 3, 1.0)          # the time step of the small recipe
+        every = int(round(10 * dt_small / dt))
+        t0 = time.perf_counter()
+        print("[bench] reflection: training the closure (six teacher runs, 2,500 Adam steps)",
+              file=sys.stderr, flush=True)
+        X, Y = teacher_samples(VXt, Et, N, 6, np.ones(Kt), np.ones(Kt), dt,
+                               np.random.default_rng(5).uniform(0.3, 0.7, size=(6, 3)), 0.15,
+                               steps=int(round(700 * dt_small / dt)), every=every,
+                               start=6 * every)
+        wts, _ = train(X, Y, iters=2500, batch=4096, lr=1e-3, seed=5)
+        print(f"[bench] reflection: closure trained on {len(Y)} samples in "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        inner["closure"] = run(VX, E, rho, c, 0, "closure", closure=wts)
     m = 2 * n
     VXo, Eo = w.kuhn_mesh(m, lo=(-0.5,) * 3, hi=(1.5,) * 3)
     rho_o, c_o = medium(m, n // 2)
@@ -200,7 +224,7 @@ def run_reflection(args):
     i, j, k = cell % n, (cell // n) % n, cell // (n * n)
     eo = (((k + n // 2) * m + (j + n // 2)) * m + (i + n // 2)) * 6 + t
     r = ref[eo]
-    err = {f"P={P}": float(np.linalg.norm(q - r) / np.linalg.norm(r)) for P, q in inner.items()}
+    err = {k: float(np.linalg.norm(q - r) / np.linalg.norm(r)) for k, q in inner.items()}
     print(json.dumps({"workload": "reflection: 40^3 x 6 layered case with its Ricker source "
                                   "against the doubled domain [-0.5, 1.5]^3 (80^3 x 6 tets, "
                                   "HABC P=6), t = 0.45",
@@ -262,8 +286,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="time the 3D launch candidates on this workload and keep the fastest")
     ap.add_argument("--closure", action="store_true",
-                    help="P = 0 with the learned boundary closure (seeded random weights: the "
-                         "cost does not depend on them)")
+                    help="P = 0 with the learned boundary closure (layered workload: seeded "
+                         "random weights, the cost does not depend on them; reflection "
+                         "workload: trained first, then evaluated)")
     ap.add_argument("--graph", action="store_true",
                     help="replayed stepping: every step runs as one captured HIP graph")
     ap.add_argument("--calib-copy", action="store_true",
