@@ -158,10 +158,12 @@ def run_reflection(args):
     t = 0.17; what the reference's own boundary reflects cannot come back
     into the unit cube before t = 0.5.  Reports the relative l2 error of q3
     over the unit cube.  With --closure the learned closure is trained first
-    (the small recipe of its test: six P = 6 teacher runs of a Gaussian
-    pulse on 8^3 x 6 tets, here at this case's N and time step, so that the
-    network's history of step ends spans the same time as in use) and
-    evaluated on the same case with P = 0."""
+    and evaluated on the same case with P = 0.  The teacher runs are P = 6
+    runs of Gaussian pulses, always at this case's N and time step, so that
+    the network's history of step ends spans the same time as in use.
+    --teacher small uses the test's small recipe (six pulses on 8^3 x 6
+    tets, c = 1); --teacher case uses four pulses on this case's own mesh
+    and medium, centred away from the source."""
     import numpy as np
     import torch
     import workloads as w
@@ -199,18 +201,26 @@ def run_reflection(args):
     inner = {f"P={P}": run(VX, E, rho, c, P, f"P={P}") for P in (6, 0)}
     if args.closure:
         from paper_1610_05023_amd.closure import teacher_samples, train
-        nt = 8
-        VXt, Et = w.kuhn_mesh(nt)
-        Kt = Et.shape[0]
-        dt_small = w.kuhn_dt(nt, 3, 1.0)          # the time step of the small recipe
-        every = int(round(10 * dt_small / dt))
         t0 = time.perf_counter()
-        print("[bench] reflection: training the closure (six teacher runs, 2,500 Adam steps)",
-              file=sys.stderr, flush=True)
-        X, Y = teacher_samples(VXt, Et, N, 6, np.ones(Kt), np.ones(Kt), dt,
-                               np.random.default_rng(5).uniform(0.3, 0.7, size=(6, 3)), 0.15,
-                               steps=int(round(700 * dt_small / dt)), every=every,
-                               start=6 * every)
+        print(f"[bench] reflection: training the closure ({args.teacher} teacher runs, "
+              "2,500 Adam steps)", file=sys.stderr, flush=True)
+        if args.teacher == "small":
+            nt = 8
+            VXt, Et = w.kuhn_mesh(nt)
+            Kt = Et.shape[0]
+            dt_small = w.kuhn_dt(nt, 3, 1.0)          # the time step of the small recipe
+            every = int(round(10 * dt_small / dt))
+            X, Y = teacher_samples(VXt, Et, N, 6, np.ones(Kt), np.ones(Kt), dt,
+                                   np.random.default_rng(5).uniform(0.3, 0.7, size=(6, 3)),
+                                   0.15, steps=int(round(700 * dt_small / dt)), every=every,
+                                   start=6 * every)
+        else:
+            # the case's own mesh and medium with P = 6: Gaussian pulses (width
+            # 0.08, about the source's wavelength) at seeded interior centres
+            # other than the source's, to the same time
+            X, Y = teacher_samples(VX, E, N, 6, rho, c, dt,
+                                   np.random.default_rng(7).uniform(0.25, 0.75, size=(4, 3)),
+                                   0.08, steps=steps, every=400, start=400)
         wts, _ = train(X, Y, iters=2500, batch=4096, lr=1e-3, seed=5)
         print(f"[bench] reflection: closure trained on {len(Y)} samples in "
               f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -289,6 +299,9 @@ def main():
                     help="P = 0 with the learned boundary closure (layered workload: seeded "
                          "random weights, the cost does not depend on them; reflection "
                          "workload: trained first, then evaluated)")
+    ap.add_argument("--teacher", choices=["small", "case"], default="small",
+                    help="reflection --closure: teacher runs of the small recipe (8^3, c = 1) "
+                         "or on the case's own mesh and medium")
     ap.add_argument("--graph", action="store_true",
                     help="replayed stepping: every step runs as one captured HIP graph")
     ap.add_argument("--calib-copy", action="store_true",
