@@ -129,19 +129,25 @@ dgh_status dgh_workspace_size(dgh_ctx* ctx, size_t* bytes);
 dgh_status dgh_bind_workspace(dgh_ctx* ctx, void* device_ptr, size_t bytes, void* stream);
 
 /* Sets the state of one shot (0 <= shot < n_shots) from host arrays in the
- * canonical layouts;
- * arrays[DGH_NARRAYS], a NULL entry means zeros.  Synchronises the stream. */
+ * canonical layouts: the initial data of the problem statement (Section 2:
+ * compactly supported initial pressure and velocity, and zero auxiliary
+ * fields, which a NULL entry gives).  arrays[DGH_NARRAYS], a NULL entry
+ * means zeros.  First waits for the work queued on the bound stream (a step
+ * in flight), then copies on that stream and waits for the copies. */
 dgh_status dgh_set_state(dgh_ctx* ctx, int shot, const double* const* arrays);
 
-/* Copies the state of one shot to host arrays (NULL entries are skipped).
- * Synchronises the stream. */
+/* Copies the state of one shot to host arrays (NULL entries are skipped):
+ * the pressure and velocity fields that Section 4.1 measures, and every
+ * auxiliary and coupling array of the boundary levels.  Waits for the work
+ * queued on the bound stream, then copies on it. */
 dgh_status dgh_read_fields(dgh_ctx* ctx, int shot, double* const* arrays);
 
 /* Point source delta(x - xs) S(t) in the pressure equation with
  * S(t) = amp (t - t0) exp(-pi^2 f0^2 (t - t0)^2), the integral of a Ricker
  * wavelet of peak frequency f0 (Section 4.1).  The source is projected on
  * the element that contains xs (the most interior one on ties).  amp = 0
- * removes the source of that shot. */
+ * removes the source of that shot.  Waits for the work queued on the bound
+ * stream before it writes, then copies on that stream. */
 dgh_status dgh_set_source(dgh_ctx* ctx, int shot, const double* xs, double f0, double t0,
                           double amp);
 
@@ -223,7 +229,8 @@ dgh_status dgh_check(dgh_ctx* ctx, int shot, double e_ref, double rel_tol, doubl
  * once per step, at its end, on the traces of that step end and the 4
  * before it (the inputs dgh_closure_sample records); its r- then holds for
  * every stage of the next step.  dgh_set_state clears a shot's trace
- * history and its r- (qb3). */
+ * history and its r- (qb3).  Waits for the work queued on the bound stream
+ * before it writes the weights. */
 dgh_status dgh_set_closure(dgh_ctx* ctx, const float* w, int n_w);
 
 /* Keeps the per-node trace history up to date at every step end (always on

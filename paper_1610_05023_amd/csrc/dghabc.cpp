@@ -119,6 +119,24 @@ T* dptr(dgh_ctx* c, const Region& r) {
   return reinterpret_cast<T*>(c->ws + r.off);
 }
 
+// Host-to-device copy and fill on the bound stream, each waited for before
+// returning: work already queued on that stream (a step in flight) finishes
+// first, and the host buffer may be reused at once.
+hipError_t h2d(dgh_ctx* c, void* dst, const void* src, size_t bytes) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+  return e != hipSuccess ? e : hipStreamSynchronize(c->stream);
+}
+
+hipError_t d2h(dgh_ctx* c, void* dst, const void* src, size_t bytes) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream);
+  return e != hipSuccess ? e : hipStreamSynchronize(c->stream);
+}
+
+hipError_t dzero(dgh_ctx* c, void* dst, size_t bytes) {
+  hipError_t e = hipMemsetAsync(dst, 0, bytes, c->stream);
+  return e != hipSuccess ? e : hipStreamSynchronize(c->stream);
+}
+
 // Builds the device-layout arrays on the host.
 struct HostArrays {
   std::vector<double> geo3, zn3, ops3, mass3, J3, ops2f;
@@ -468,7 +486,7 @@ hipError_t upload(dgh_ctx* c, const Region& r, const V& v) {
   if (v.empty()) return hipSuccess;
   const size_t b = v.size() * sizeof(v[0]);
   if (b > r.bytes) return hipErrorInvalidValue;
-  return hipMemcpy(c->ws + r.off, v.data(), b, hipMemcpyHostToDevice);
+  return h2d(c, c->ws + r.off, v.data(), b);
 }
 
 void fill_levels(dgh_ctx* c) {
@@ -753,6 +771,7 @@ dgh_status dgh_set_state(dgh_ctx* c, int shot, const double* const* arr) {
   const Layout& L = c->lay;
   const int Np = m.tet.Np;
   const int cur = c->cur;
+  HIPCHECK(c, hipStreamSynchronize(c->stream));   // no step still reads or writes the state
   std::vector<double> buf((size_t)c->ntile * 4 * Np * dgh::kTile);
   for (int which : {DGH_Q3, DGH_RES3}) {
     if (arr && arr[which])
@@ -763,9 +782,9 @@ dgh_status dgh_set_state(dgh_ctx* c, int shot, const double* const* arr) {
     char* dst = c->ws + r.off + shot * L.st3 * L.e3;
     if (L.e3 == 4) {   // FP32 state: rounded on upload
       std::vector<float> f(buf.begin(), buf.end());
-      HIPCHECK(c, hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+      HIPCHECK(c, h2d(c, dst, f.data(), f.size() * sizeof(float)));
     } else {
-      HIPCHECK(c, hipMemcpy(dst, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+      HIPCHECK(c, h2d(c, dst, buf.data(), buf.size() * sizeof(double)));
     }
   }
   struct Item { int idx; const Region* r; size_t n, stride; };
@@ -785,17 +804,16 @@ dgh_status dgh_set_state(dgh_ctx* c, int shot, const double* const* arr) {
     if (it.n == 0) continue;
     char* dst = c->ws + it.r->off + shot * it.stride * sizeof(double);
     if (arr && arr[it.idx]) {
-      HIPCHECK(c, hipMemcpy(dst, arr[it.idx], it.n * sizeof(double), hipMemcpyHostToDevice));
+      HIPCHECK(c, h2d(c, dst, arr[it.idx], it.n * sizeof(double)));
     } else {
-      HIPCHECK(c, hipMemset(dst, 0, it.n * sizeof(double)));
+      HIPCHECK(c, dzero(c, dst, it.n * sizeof(double)));
     }
   }
   // a new state has no past: the closure's trace history starts at zero
   const size_t nn = (size_t)m.Ktri * m.tri.Np;
   if (nn > 0)
-    HIPCHECK(c, hipMemset(c->ws + L.hist.off + shot * nn * 10 * sizeof(float), 0,
-                          nn * 10 * sizeof(float)));
-  HIPCHECK(c, hipDeviceSynchronize());
+    HIPCHECK(c, dzero(c, c->ws + L.hist.off + shot * nn * 10 * sizeof(float),
+                      nn * 10 * sizeof(float)));
   return DGH_OK;
 }
 
@@ -814,10 +832,10 @@ dgh_status dgh_read_fields(dgh_ctx* c, int shot, double* const* arr) {
     const char* src = c->ws + r.off + shot * L.st3 * L.e3;
     if (L.e3 == 4) {
       std::vector<float> f(buf.size());
-      HIPCHECK(c, hipMemcpy(f.data(), src, f.size() * sizeof(float), hipMemcpyDeviceToHost));
+      HIPCHECK(c, d2h(c, f.data(), src, f.size() * sizeof(float)));
       std::copy(f.begin(), f.end(), buf.begin());
     } else {
-      HIPCHECK(c, hipMemcpy(buf.data(), src, buf.size() * sizeof(double), hipMemcpyDeviceToHost));
+      HIPCHECK(c, d2h(c, buf.data(), src, buf.size() * sizeof(double)));
     }
     from_tiles(buf.data(), arr[which], c->slot2elem, Np);
   }
@@ -835,8 +853,8 @@ dgh_status dgh_read_fields(dgh_ctx* c, int shot, double* const* arr) {
   };
   for (const Item& it : items)
     if (arr[it.idx] && it.n)
-      HIPCHECK(c, hipMemcpy(arr[it.idx], c->ws + it.r->off + shot * it.stride * sizeof(double),
-                            it.n * sizeof(double), hipMemcpyDeviceToHost));
+      HIPCHECK(c, d2h(c, arr[it.idx], c->ws + it.r->off + shot * it.stride * sizeof(double),
+                      it.n * sizeof(double)));
   return DGH_OK;
 }
 
@@ -846,11 +864,12 @@ dgh_status dgh_set_source(dgh_ctx* c, int shot, const double* xs, double f0, dou
   if (shot < 0 || shot >= c->n_shots) return fail(c, DGH_EINVAL, "shot out of range");
   if (!std::isfinite(f0) || !std::isfinite(t0) || !std::isfinite(amp))
     return fail(c, DGH_EINVAL, "source parameters must be finite");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));   // no step still reads the source
   if (amp == 0.0) {
     c->src_slot[shot] = -1;
     const double par[4] = {-1.0, 0.0, 0.0, 0.0};
-    HIPCHECK(c, hipMemcpy(c->ws + c->lay.srcp.off + (size_t)shot * 4 * sizeof(double), par,
-                          sizeof(par), hipMemcpyHostToDevice));
+    HIPCHECK(c, h2d(c, c->ws + c->lay.srcp.off + (size_t)shot * 4 * sizeof(double), par,
+                    sizeof(par)));
     return DGH_OK;
   }
   const dgh::Mesh& m = c->mesh;
@@ -880,12 +899,12 @@ dgh_status dgh_set_source(dgh_ctx* c, int shot, const double* xs, double f0, dou
     for (int k = 0; k < Np; ++k) w[a] += m.tet.V[a * Np + k] * psi[k];
     w[a] /= m.J[best];
   }
-  HIPCHECK(c, hipMemcpy(c->ws + c->lay.srcw.off + (size_t)shot * Np * sizeof(double), w.data(),
-                        Np * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHECK(c, h2d(c, c->ws + c->lay.srcw.off + (size_t)shot * Np * sizeof(double), w.data(),
+                  Np * sizeof(double)));
   c->src_slot[shot] = c->elem2slot[best];
   const double par[4] = {(double)c->src_slot[shot], f0, t0, amp};
-  HIPCHECK(c, hipMemcpy(c->ws + c->lay.srcp.off + (size_t)shot * 4 * sizeof(double), par,
-                        sizeof(par), hipMemcpyHostToDevice));
+  HIPCHECK(c, h2d(c, c->ws + c->lay.srcp.off + (size_t)shot * 4 * sizeof(double), par,
+                  sizeof(par)));
   return DGH_OK;
 }
 
@@ -1164,7 +1183,9 @@ dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, d
   const long long total = first;
   dgh::Member3* dev = dptr<dgh::Member3>(c0, c0->lay.grp);
   HIPCHECK(c0, hipStreamSynchronize(st));
-  HIPCHECK(c0, hipMemcpy(dev, hd.data(), hd.size() * sizeof(dgh::Member3), hipMemcpyHostToDevice));
+  HIPCHECK(c0, hipMemcpyAsync(dev, hd.data(), hd.size() * sizeof(dgh::Member3),
+                              hipMemcpyHostToDevice, st));
+  HIPCHECK(c0, hipStreamSynchronize(st));
   for (int it = 0; it < n_steps; ++it) {
     const double t = t_start + it * dt;
     for (int s = 0; s < 5; ++s) {
@@ -1287,8 +1308,8 @@ dgh_status dgh_set_closure(dgh_ctx* c, const float* w, int n_w) {
     if (!std::isfinite(w[i])) return fail(c, DGH_EINVAL, "closure parameters must be finite");
   if (!(std::fabs(w[1]) <= 1.0f))
     return fail(c, DGH_EINVAL, "closure gain bound |g_max| must not exceed 1");
-  HIPCHECK(c, hipMemcpy(c->ws + c->lay.mlpw.off, w, (size_t)n_w * sizeof(float),
-                        hipMemcpyHostToDevice));
+  HIPCHECK(c, hipStreamSynchronize(c->stream));   // no step still reads the weights
+  HIPCHECK(c, h2d(c, c->ws + c->lay.mlpw.off, w, (size_t)n_w * sizeof(float)));
   c->closure = true;
   return DGH_OK;
 }

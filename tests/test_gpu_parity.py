@@ -461,6 +461,39 @@ def test_checkpoint_resume_is_bitwise():
         assert np.array_equal(want[k], got[k]), k
 
 
+def _side_stream_sequence(stream):
+    """Steps, then writes a new state and a new source while the steps are
+    still queued, stepping again after each write."""
+    from paper_1610_05023_amd import Solver
+    n, N, P, dt = 8, 4, 3, 2e-4
+    case = make_case(n=n, N=N, P=P, medium="layered", init="random", seed=81)
+    s = Solver(case["VX"], case["E"], case["N"], case["P"], case["rho"], case["c"],
+               face_bc=case["face_bc"], periodic=case["periodic"], box=case["box"])
+    s.bind(stream=stream)
+    s.set_state(case["state"])
+    s.set_source((0.41, 0.52, 0.47), 8.0, 0.05)
+    second = {k: 0.5 * v[::-1] for k, v in case["state"].items()}
+    s.step(60, dt, 0.0)
+    s.set_state(second)                        # must wait for the 60 steps
+    s.step(20, dt, 0.0)
+    s.set_source((0.6, 0.4, 0.55), 6.0, 0.02)  # must wait for the 20 steps
+    s.step(20, dt, 20 * dt)
+    return s.read_fields()
+
+
+def test_state_and_source_writes_wait_for_a_side_stream():
+    """Bound to a torch side stream (non-blocking with respect to the null
+    stream), set_state and set_source issued while steps are still queued
+    must take effect after them: the results equal the same sequence on the
+    default stream bitwise."""
+    import torch
+    want = _side_stream_sequence(None)
+    side = torch.cuda.Stream(device=0)
+    got = _side_stream_sequence(side)
+    for k in want:
+        assert np.array_equal(want[k], got[k]), k
+
+
 @pytest.mark.parametrize("precision", [0, 2])
 def test_group_step_equals_separate_runs(precision):
     """An uneven group (meshes of 3^3, 4^3 and 5^3 cells, one of them with
