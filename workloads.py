@@ -102,6 +102,29 @@ def general_mesh(n, amp=0.1, seed=0, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
     return VX, np.ascontiguousarray(E, dtype=np.int32)
 
 
+def mirror_doubled_mesh(VX, EToV, axis=2, plane=None):
+    """The mesh together with its mirror image in the plane x_axis = plane
+    (default: the mesh's largest coordinate on that axis): vertices on the
+    plane are shared, mirrored elements have two vertices swapped so that
+    every element stays positively oriented.  Returns (VX2, EToV2, img):
+    the first K elements are the given ones in order, element K + k is the
+    image of element k, and img[v] is the vertex id of the image of
+    vertex v."""
+    VX = np.asarray(VX, dtype=np.float64)
+    EToV = np.asarray(EToV, dtype=np.int64)
+    if plane is None:
+        plane = float(VX[:, axis].max())
+    on = np.abs(VX[:, axis] - plane) <= 1e-12 * max(1.0, abs(plane))
+    img = np.empty(VX.shape[0], dtype=np.int64)
+    img[on] = np.nonzero(on)[0]
+    off = np.nonzero(~on)[0]
+    img[off] = VX.shape[0] + np.arange(off.size)
+    VXm = VX[off].copy()
+    VXm[:, axis] = 2.0 * plane - VXm[:, axis]
+    Em = img[EToV][:, [0, 1, 3, 2]]
+    return (np.concatenate([VX, VXm]), np.concatenate([EToV, Em]).astype(np.int32), img)
+
+
 def cell_index_of_element(n, dims=None):
     """(i, j, k) cell indices of every element of ``kuhn_mesh``."""
     nx, ny, nz = dims if dims is not None else (n, n, n)
