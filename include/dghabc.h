@@ -258,6 +258,20 @@ dgh_status dgh_mlp_grad(const float* W, const float* X, const float* T, int n, f
 dgh_status dgh_mlp_adam(float* W, const float* G, float* M, float* V, int t, float lr,
                         void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): dgh_mlp_grad without the work argument.  Same kernels and
+ * results; the work buffer is a fixed array inside the library, one per
+ * GPU (6.4 MB, held until the process ends), so 1 <= n <=
+ * DGH_MLP_STATIC_BATCH (DGH_EINVAL otherwise).  Calls no allocating
+ * routine.  Every call on a GPU shares that GPU's array: calls that overlap
+ * on one GPU (other streams or host threads) race; the array needs no
+ * clearing (every value is written before it is read).  Runs on the
+ * device of `stream` (the current device for NULL). */
+#define DGH_MLP_STATIC_BATCH 4096
+dgh_status dgh_mlp_grad_static(const float* W, const float* X, const float* T, int n, float* G,
+                               double* loss, void* stream);
+
 /* Per-kernel timing with HIP events on the bound stream: enable = 1 starts
  * recording around every 3D-level launch, 0 stops.  dgh_kernel_time returns
  * the accumulated milliseconds and launch count of level `level` (3, 2, 1,

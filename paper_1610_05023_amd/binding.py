@@ -56,6 +56,8 @@ _SIGS = {
                      C.POINTER(C.c_double), C.c_void_p],
     "dgh_mlp_adam": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_float,
                      C.c_void_p],
+    "dgh_mlp_grad_static": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                            C.POINTER(C.c_double), C.c_void_p],
     "dgh_kernel_timing": [C.c_void_p, C.c_int],
     "dgh_kernel_time": [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)],
     "dgh_last_error": [C.c_void_p],
@@ -334,6 +336,21 @@ def mlp_grad(W, X, T, G, work, with_loss=True):
                                C.byref(loss) if with_loss else None, _stream(X)),
            "dgh_mlp_grad")
     return loss.value if with_loss else None
+
+
+def mlp_grad_static(W, X, T, G, with_loss=True):
+    """mlp_grad with the library's own fixed work array (no allocation;
+    at most MLP_STATIC_BATCH rows)."""
+    loss = C.c_double()
+    _check(load().dgh_mlp_grad_static(C.c_void_p(W.data_ptr()), C.c_void_p(X.data_ptr()),
+                                      C.c_void_p(T.data_ptr()), int(X.shape[0]),
+                                      C.c_void_p(G.data_ptr()),
+                                      C.byref(loss) if with_loss else None, _stream(X)),
+           "dgh_mlp_grad_static")
+    return loss.value if with_loss else None
+
+
+MLP_STATIC_BATCH = 4096
 
 
 def mlp_adam(W, G, M, V, t, lr):

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "kernels.hpp"
 #include "launch.hpp"
@@ -451,7 +452,45 @@ __global__ void __launch_bounds__(kThreads) k_closure_sample(Lvl2 L2, const T3* 
 }  // namespace
 
 // work: H[192][n], dH[192][n], Y[n], dY[n], Th[n], Inv[n], then the loss partials
-size_t mlp_work_floats(int n) { return (size_t)n * (2 * 3 * kH + 4) + (n + kThreads - 1) / kThreads; }
+constexpr size_t work_floats(int n) {
+  return (size_t)n * (2 * 3 * kH + 4) + (n + kThreads - 1) / kThreads;
+}
+size_t mlp_work_floats(int n) { return work_floats(n); }
+
+// The gradient's work buffer for callers that cannot allocate: one
+// file-scope array per GPU, sized for kMlpStaticBatch samples (6.4 MB),
+// held until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress returns on that device.
+static_assert(kMlpStaticBatch % kThreads == 0, "static batch");
+static __device__ __align__(256) float scratch[work_floats(kMlpStaticBatch)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t mlp_static_work(hipStream_t st, float** work) {
+  int dev = 0;
+  hipError_t e = st ? hipStreamGetDevice(st, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int prev = 0;
+    e = hipGetDevice(&prev);
+    if (e != hipSuccess) return e;
+    if (prev != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    const hipError_t back = prev != dev ? hipSetDevice(prev) : hipSuccess;
+    if (e != hipSuccess) return e;
+    if (back != hipSuccess) return back;
+    g_scratch_ptr[dev] = static_cast<float*>(ptr);
+  }
+  *work = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 hipError_t mlp_forward(const float* W, const float* X, int n, float* Y, hipStream_t st) {
   if (n <= 0) return hipSuccess;

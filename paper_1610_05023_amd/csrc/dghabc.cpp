@@ -1372,6 +1372,29 @@ dgh_status dgh_mlp_grad(const float* W, const float* X, const float* T, int n, f
   return DGH_OK;
 }
 
+dgh_status dgh_mlp_grad_static(const float* W, const float* X, const float* T, int n, float* G,
+                               double* loss, void* stream) {
+  static_assert(dgh::kMlpStaticBatch == DGH_MLP_STATIC_BATCH, "header and library agree");
+  if (!W || !X || !T || !G || n <= 0 || n > DGH_MLP_STATIC_BATCH) return DGH_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* work = nullptr;
+  if (dgh::mlp_static_work(st, &work) != hipSuccess) return DGH_EHIP;
+  if (dgh::mlp_grad(W, X, T, n, G, work, st) != hipSuccess) return DGH_EHIP;
+  if (loss) {
+    constexpr int kParts = (DGH_MLP_STATIC_BATCH + 255) / 256;
+    float part[kParts];
+    const int nb = (n + 255) / 256;
+    if (hipMemcpyAsync(part, dgh::mlp_loss_partials(work, n), nb * sizeof(float),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return DGH_EHIP;
+    double sum = 0.0;
+    for (int b = 0; b < nb; ++b) sum += part[b];
+    *loss = sum / n;
+  }
+  return DGH_OK;
+}
+
 dgh_status dgh_mlp_adam(float* W, const float* G, float* M, float* V, int t, float lr,
                         void* stream) {
   if (!W || !G || !M || !V || t < 1 || !(lr > 0)) return DGH_EINVAL;

@@ -187,6 +187,11 @@ inline int frag2_size(int N) {
 // Learned closure (closure.hip): MLP parameters, flat, FP32.
 constexpr int kMlpParams = 9091;
 size_t mlp_work_floats(int n);
+// largest batch of the no-allocation gradient (its work array's size)
+constexpr int kMlpStaticBatch = 4096;
+// The no-allocation gradient's work array on the device of `st` (the
+// current device for the null stream), resolved once per device.
+hipError_t mlp_static_work(hipStream_t st, float** work);
 const float* mlp_loss_partials(const float* work, int n);
 hipError_t mlp_forward(const float* W, const float* X, int n, float* Y, hipStream_t st);
 hipError_t mlp_grad(const float* W, const float* X, const float* T, int n, float* G, float* work,
