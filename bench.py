@@ -36,6 +36,22 @@ def bytes_per_tet_stage(Np, word=8):
     return 16 * Np * word + 27 * 8 + 20
 
 
+def bytes_per_stage(K, Ktri, Klin, N, P, word3=8, shots=1):
+    """Algorithmic HBM bytes of one RK stage over all levels: the 3D level as
+    above; per triangle q2 and res2 read and written (4 P 3 Np2 FP64 words)
+    and 4 coupling words per node (the new 3D trace read, qb3 and q0_3
+    written); per line q1 and res1 read and written (4 P^2 2 Np1 words).
+    Per-tet constants are counted once per shot (the kernels re-read them
+    per shot)."""
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    Np2 = (N + 1) * (N + 2) // 2
+    Np1 = N + 1
+    b3 = K * bytes_per_tet_stage(Np, word3)
+    b2 = Ktri * (4 * P * 3 * Np2 + 4 * Np2) * 8
+    b1 = Klin * 4 * P * P * 2 * Np1 * 8
+    return (b3 + b2 + b1) * shots
+
+
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_level3_layered40_traffic.txt")
 KERNEL3_SOURCES = ["levels_fp64.hip", "kernels.hpp", "levels.hpp"]
 
@@ -105,6 +121,8 @@ def run_uneven(args):
     from paper_1610_05023_amd import Solver
     from paper_1610_05023_amd.binding import step_group
     N, P, sizes = 4, 3, (10, 16, 24)
+    if args.precision == "bf16":
+        sys.exit("bench.py: the uneven group runs FP64 or FP32 (the BF16 variant has no group kernel)")
     prec = 2 if args.precision == "fp32" else 0
     solvers, U = [], 0
     xs = w.shot_positions(len(sizes), seed=6)
@@ -178,10 +196,16 @@ def run_reflection(args):
         layer = np.searchsorted(cuts, np.clip(k - shift, 0, n - 1), side="right")
         return rvals[layer].copy(), cvals[layer].copy()
 
+    # the closure's time scales: the library's default for this case's mesh
+    # (1.25, 2.5, 5, 10 cell crossings at the fastest speed), shared by the
+    # teacher runs and the evaluation
+    tau = [1.25 * 2 ** k * (1.0 / n) / float(cvals.max()) for k in range(4)]
+
     def run(VX, E, rho, c, P, label, closure=None):
         t0 = time.perf_counter()
         s = Solver(VX, E, N, P, rho, c).bind()
         if closure is not None:
+            s.set_closure_memory(tau)
             s.set_closure(closure)
         s.set_source(cfg.source, cfg.f0, cfg.t0)
         done = 0
@@ -213,14 +237,14 @@ def run_reflection(args):
             X, Y = teacher_samples(VXt, Et, N, 6, np.ones(Kt), np.ones(Kt), dt,
                                    np.random.default_rng(5).uniform(0.3, 0.7, size=(6, 3)),
                                    0.15, steps=int(round(700 * dt_small / dt)), every=every,
-                                   start=6 * every)
+                                   start=6 * every, tau=tau)
         else:
             # the case's own mesh and medium with P = 6: Gaussian pulses (width
             # 0.08, about the source's wavelength) at seeded interior centres
             # other than the source's, to the same time
             X, Y = teacher_samples(VX, E, N, 6, rho, c, dt,
                                    np.random.default_rng(7).uniform(0.25, 0.75, size=(4, 3)),
-                                   0.08, steps=steps, every=400, start=400)
+                                   0.08, steps=steps, every=400, start=400, tau=tau)
         wts, _ = train(X, Y, iters=2500, batch=4096, lr=1e-3, seed=5)
         print(f"[bench] reflection: closure trained on {len(Y)} samples in "
               f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -243,20 +267,90 @@ def run_reflection(args):
                       "reference_q3_norm": float(np.linalg.norm(r))}))
 
 
-def cpu_baseline(seconds_target=20.0):
+def run_validation(args):
+    """Section 4.1's validation benchmark on a Kuhn stand-in for the paper's
+    70,895-tet mesh: 23^3 x 6 = 73,002 tets of [-0.5, 0.5]^3, N = 3,
+    rho = c = 1, the Ricker source (f0 = 2.5, t0 = 0.5) at the centre and at
+    (0.2, 0.1, 0), HABC orders 0 (the basic ABC), 2, 4, ..., 12 on all six
+    faces (or, with --free-surface, p = 0 on z = 0.5 and HABC on the other
+    five faces, against the image solution), stepped on the GPU in FP64 to
+    t = --t-final.  Error(t) is the paper's relative energy norm against the
+    free-space (or image) solution, with the Dirichlet run's energy as
+    denominator, both integrated by a degree-7 quadrature on every tet.
+    Prints one JSON line with the curves (every --sample time units)."""
+    import numpy as np
+    import workloads as w
+    from paper_1610_05023_amd.validation import run_benchmark
+    n, N = args.valid_n, 3
+    VX, E = w.kuhn_mesh(n, lo=(-0.5,) * 3, hi=(0.5,) * 3)
+    dt = w.kuhn_dt(n, N, 1.0)
+    orders = tuple(int(v) for v in args.orders.split(","))
+    extra = {}
+    if args.matched and 3 not in orders:
+        orders = tuple(sorted(orders + (3,)))     # the Pade condition of the same order
+    if args.matched:
+        # coefficients making the P = 3 condition exact at 20, 38 and 52
+        # degrees, the incidences a centred source produces on the faces
+        from paper_1610_05023_amd.habc_params import angle_matched_gamma
+        extra["P=3 matched 20,38,52 deg"] = (3, angle_matched_gamma(np.radians([20, 38, 52])))
+    t_start = time.perf_counter()
+    res = run_benchmark(VX, E, dt, N=N, orders=orders, free_surface=args.free_surface,
+                        t_final=args.t_final, sample=args.sample, extra=extra,
+                        log=lambda m: print(f"[bench] validation {m}", file=sys.stderr,
+                                            flush=True))
+    labels = [(P, f"P={P}") for P in orders] + [(k, k) for k in extra]
+    out = {"workload": ("validation benchmark, Section 4.1: " + (
+        "free surface p = 0 on z = 0.5, HABC on the other faces, image solution"
+        if args.free_surface else "HABC on all faces, free-space solution") +
+        f"; Kuhn mesh {n}^3 x 6 = {E.shape[0]} tets of [-0.5, 0.5]^3, N = {N}, rho = c = 1, "
+        "Ricker f0 = 2.5, t0 = 0.5, FP64"), "dt": dt, "orders": list(orders),
+        "wall_s": time.perf_counter() - t_start, "sources": {}}
+    for xs, rec in res.items():
+        curves = {lab: [round(float(v), 6) for v in rec[key]] for key, lab in labels}
+        summary = {}
+        for key, lab in labels:
+            e = np.array(rec[key])
+            tt = np.array(rec["times"])
+            after = tt >= 1.0
+            summary[lab] = {"error_at_t1": float(np.interp(1.0, tt, e)),
+                                 "min_after_t1": float(e[after].min()),
+                                 "t_of_min": float(tt[after][np.argmin(e[after])]),
+                                 "max_after_t1": float(e[after].max()),
+                                 "final": float(e[-1])}
+        out["sources"][str(list(xs))] = {"E_src": rec["E_src"],
+                                         "E_src_library": rec["E_src_library"],
+                                         "times": [round(float(t), 6) for t in rec["times"]],
+                                         "error": curves, "summary": summary}
+    print(json.dumps(out))
+
+
+def _host_cpu():
+    """Host CPU count and model (as the kernel reports them)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count(), model
+
+
+def cpu_baseline():
     """The FP64 oracle (numpy, as is) on a bounded sample of the workload:
     the same medium recipe, degree and HABC order on a 20^3 x 6 = 48,000-tet
-    mesh, stepped for 10 steps (50 RK stages, about 10 s).  Per-element work is the same
-    as on the 40^3 mesh, so DOF-updates/s per stage carries over."""
+    mesh, stepped for 5 steps (25 RK stages), once with numpy's BLAS limited
+    to one thread (the reported value: the oracle is mostly single-threaded
+    elementwise numpy, so this is what one core does) and once with the BLAS
+    pool as numpy starts it.  Per-element work is the same as on the 40^3
+    mesh, so DOF-updates/s per stage carries over."""
     import numpy as np
     import workloads as w
     from oracle.solver import Oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = 1
-    n, N, P, steps = 20, 4, 6, 10
+    from threadpoolctl import threadpool_info, threadpool_limits
+    blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    n, N, P, steps = 20, 4, 6, 5
     VX, E = w.kuhn_mesh(n)
     rho, c, *_ = w.layered_medium(n, seed=2)
     o = Oracle(VX, E, N, P, rho, c)
@@ -264,17 +358,24 @@ def cpu_baseline(seconds_target=20.0):
     xs = (0.5 + 0.3 * h, 0.5 + 0.2 * h, 0.5 + 0.1 * h)
     f0 = float(w.source_material(n, xs, c)) / (10.0 * h)
     o.set_source(xs, f0, 1.25 / f0)
-    o.s["q3"] = w.random_array(o.s["q3"].shape, 1) * 1e-3
     dt = w.kuhn_dt(n, N, float(c.max()))
-    t = time.perf_counter()
-    o.step(steps, dt)
-    el = time.perf_counter() - t
     U = w.n_unknowns(o.m.K, o.m.Ktri, o.m.Klin, N, P)
-    return {"value": U * 5 * steps / el, "unit": "DOF-updates/s", "cores": int(threads),
-            "kind": "oracle",
+    rates = {}
+    for label, limit in (("one", 1), ("all", None)):
+        o.reset()
+        o.s["q3"] = w.random_array(o.s["q3"].shape, 1) * 1e-3
+        with threadpool_limits(limits=limit):
+            t = time.perf_counter()
+            o.step(steps, dt)
+            rates[label] = (U * 5 * steps / (time.perf_counter() - t),
+                            time.perf_counter() - t)
+    cpus, model = _host_cpu()
+    return {"value": rates["one"][0], "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"numpy FP64 oracle, {o.m.K}-tet (20^3 x 6) mesh, N={N}, P={P}, same "
                       f"layered medium and source recipe, {steps} steps ({5 * steps} RK stages) "
-                      f"in {el:.1f} s"}
+                      f"in {rates['one'][1]:.1f} s with BLAS on one thread",
+            "all_threads_value": rates["all"][0], "all_threads_blas": int(blas),
+            "all_threads_seconds": rates["all"][1], "host_cpus": cpus, "host_cpu_model": model}
 
 
 def main():
@@ -284,13 +385,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=40)
-    ap.add_argument("--workload", choices=["layered", "batch", "uneven", "reflection"],
+    ap.add_argument("--workload", choices=["layered", "batch", "uneven", "reflection",
+                                           "validation"],
                     default="layered",
                     help="layered: the 40^3 layered-medium step (default); batch: 64 shots "
                          "on a 20^3 mesh stepped together")
     ap.add_argument("--shots", type=int, default=64)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
-                    help="fp32: FP32 3D level on FP32 MFMA, FP64 boundary levels")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64",
+                    help="fp32: FP32 3D state and contractions on the FP32 MFMA; bf16: FP32 "
+                         "3D state with the contractions on the BF16 MFMA; FP64 boundary "
+                         "levels in both")
     ap.add_argument("--order", type=int, default=None, help="override the degree N")
     ap.add_argument("--habc", type=int, default=None, help="override the HABC order P")
     ap.add_argument("--autotune", action="store_true",
@@ -302,8 +406,22 @@ def main():
     ap.add_argument("--teacher", choices=["small", "case"], default="small",
                     help="reflection --closure: teacher runs of the small recipe (8^3, c = 1) "
                          "or on the case's own mesh and medium")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="--autotune: JSON file of stored choices (default: "
+                         "$DGHABC_TUNING_CACHE or ~/.cache/dghabc/tuning.json)")
     ap.add_argument("--graph", action="store_true",
                     help="replayed stepping: every step runs as one captured HIP graph")
+    ap.add_argument("--valid-n", type=int, default=23,
+                    help="validation: cells per axis of the Kuhn mesh of [-0.5, 0.5]^3")
+    ap.add_argument("--orders", default="0,2,4,6,8,10,12",
+                    help="validation: HABC orders (0 = basic ABC)")
+    ap.add_argument("--free-surface", action="store_true",
+                    help="validation: p = 0 on z = 0.5, HABC on the other faces")
+    ap.add_argument("--matched", action="store_true",
+                    help="validation: add HABC P = 3 with coefficients matched to 20, 38 and "
+                         "52 degrees")
+    ap.add_argument("--t-final", type=float, default=5.0)
+    ap.add_argument("--sample", type=float, default=0.25)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run 1 GiB reference kernels first (for PMC byte counters)")
     args = ap.parse_args()
@@ -328,6 +446,8 @@ def main():
         del x, y
     if args.workload == "reflection":
         return run_reflection(args)
+    if args.workload == "validation":
+        return run_validation(args)
     if args.workload == "uneven":
         run_uneven(args)
         return
@@ -347,7 +467,7 @@ def main():
         wl["P"] = 0
     K = wl["E"].shape[0]
     t_setup = time.perf_counter()
-    prec = 2 if args.precision == "fp32" else 0
+    prec = {"fp64": 0, "fp32": 2, "bf16": 3}[args.precision]
     s = Solver(wl["VX"], wl["E"], wl["N"], wl["P"], wl["rho"], wl["c"], device=0,
                n_shots=nsh, precision=prec).bind()
     if batch:
@@ -367,9 +487,12 @@ def main():
         s.set_closure(wts)
     tuned = None
     if args.autotune:
-        best, ms = s.autotune(10)
-        tuned = {"candidate": best, "ms_per_launch": [round(float(v), 4) for v in ms]}
-        print(f"[bench] autotune: candidate {best} of {list(np.round(ms, 4))} ms",
+        from paper_1610_05023_amd.tuning import tune
+        best, ms, cached = tune(s, args.tuning_cache, 10)
+        tuned = {"candidate": best, "from_cache": cached,
+                 "ms_per_launch": None if ms is None else [round(float(v), 4) for v in ms]}
+        print(f"[bench] autotune: candidate {best}"
+              + (" (stored)" if cached else f" of {list(np.round(ms, 4))} ms"),
               file=sys.stderr, flush=True)
     if args.graph:
         s.set_graph(True)               # each step replays one captured HIP graph
@@ -396,6 +519,10 @@ def main():
     # per-tet constants are read once per shot in this kernel
     alg = bytes_per_tet_stage(k["Np"], 4 if prec else 8) * K * nsh
     achieved = achieved_gbs(alg, avg3_ms)
+    # the whole step against the same peak: all levels' algorithmic bytes
+    step_alg = 5 * bytes_per_stage(K, k["Ktri"], k["Klin"], wl["N"], wl["P"],
+                                   4 if prec else 8, nsh)
+    step_gbs = step_alg / (el / args.steps) / 1e9
     print(f"[bench] {args.steps} steps in {el:.3f} s; 3D kernel avg {avg3_ms * 1e3:.1f} us over "
           f"{n3} launches; {achieved_gbs(alg, avg3_ms):.0f} GB/s; check={finite}",
           file=sys.stderr, flush=True)
@@ -408,6 +535,7 @@ def main():
             cpu = cpu_baseline()
         except Exception as ex:  # reported, never fatal for the GPU figure
             cpu = {"value": None, "error": repr(ex)}
+    ptag = {0: "FP64", 2: "FP32-3D", 3: "BF16-contraction FP32-3D"}[prec]
     out = {
         "metric": METRIC,
         "value": value,
@@ -419,14 +547,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == 0 else "f32 (3D level) + f64 (boundary levels)",
+        "dtype": {0: "f64", 2: "f32 (3D level) + f64 (boundary levels)",
+                  3: "bf16 contractions, f32 3D state + f64 (boundary levels)"}[prec],
         "data": "synthetic",
-        "config": ({"workload": f"{'FP64' if prec == 0 else 'FP32-3D'} DG+HABC step, {args.n}^3 x 6 "
+        "config": ({"workload": f"{ptag} DG+HABC step, {args.n}^3 x 6 "
                                 f"= {K}-tet Kuhn mesh of the unit cube, N={wl['N']}, HABC "
                                 f"P={wl['P']} with edges and corners, 5 random layers (seed 2), "
                                 f"Ricker point source"}
                    if not batch else
-                   {"workload": f"{'FP64' if prec == 0 else 'FP32-3D'} DG+HABC step, {nsh} shots "
+                   {"workload": f"{ptag} DG+HABC step, {nsh} shots "
                                 f"stepped together on a {wl['n']}^3 x 6 = {K}-tet Kuhn mesh, "
                                 f"N={wl['N']}, HABC P={wl['P']}, rho=c=1, one Ricker source per "
                                 f"shot (seed 4)",
@@ -441,10 +570,14 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
-                     "kernel": ("k_level3_dma" if wl["N"] <= 4 and prec == 0 else
-                                "k_level3_f32" if prec != 0 else "k_level3") +
-                               " (3D volume + surface + LSRK update)",
-                     "avg_us": avg3_ms * 1e3, "alg_bytes_per_launch": alg},
+                     "kernel": ({0: "k_level3_dma" if wl["N"] <= 4 else "k_level3",
+                                 2: "k_level3_f32_dma" if wl["N"] <= 4 else "k_level3_f32",
+                                 3: "k_level3_bf16"}[prec] +
+                                " (3D volume + surface + LSRK update)"),
+                     "avg_us": avg3_ms * 1e3, "alg_bytes_per_launch": alg,
+                     "step_achieved": step_gbs, "step_frac": step_gbs / HBM_PEAK_GBS,
+                     "step_alg_bytes": step_alg,
+                     "step_note": "all levels' algorithmic bytes per step / ms_per_step"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

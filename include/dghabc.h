@@ -59,12 +59,15 @@ typedef enum {
 } dgh_status;
 
 /* Arithmetic of the 3D level (Section 3.2's volume, surface and update):
- * DGH_FP64, or DGH_FP32_MFMA: FP32 3D state and residual with the volume
- * and LIFT contractions on the FP32 MFMA (FP32 accumulation).  The face,
- * edge and corner levels, their RK accumulation and the energy stay FP64 in
- * both.  The FP32 variant's results differ from FP64 by rounding only; its
- * error is reported by the tests, not bounded by the FP64 parity target. */
-typedef enum { DGH_FP64 = 0, DGH_FP32_MFMA = 2 } dgh_precision;
+ * DGH_FP64; DGH_FP32_MFMA: FP32 3D state and residual with the volume and
+ * LIFT contractions on the FP32 MFMA (FP32 accumulation); DGH_BF16_MFMA:
+ * the same FP32 state, residual, fluxes and update, with the volume and
+ * LIFT contractions on the BF16 MFMA (operators and the values entering
+ * each contraction rounded to BF16, FP32 accumulation).  The face, edge and
+ * corner levels, their RK accumulation and the energy stay FP64 in all.
+ * The mixed forms differ from FP64 by rounding only; their errors are
+ * reported by the tests, not bounded by the FP64 parity target. */
+typedef enum { DGH_FP64 = 0, DGH_FP32_MFMA = 2, DGH_BF16_MFMA = 3 } dgh_precision;
 
 /* Boundary condition of a face of the cuboid (faces x-, x+, y-, y+, z-, z+).
  * HABC: Pade HABC of order P (Section 2), with edge/corner compatibility where
@@ -85,8 +88,8 @@ enum {
   DGH_C_P, DGH_C_N, DGH_C_NSHOTS, DGH_NCOUNTS
 };
 
-/* Creates a context for HIP device `device`.  precision: DGH_FP64 or
- * DGH_FP32_MFMA (dgh_precision).
+/* Creates a context for HIP device `device`.  precision: DGH_FP64,
+ * DGH_FP32_MFMA or DGH_BF16_MFMA (dgh_precision).
  * n_shots (1..4096): independent problems on the same mesh and medium,
  * each with its own state and point source, stepped together: every launch
  * covers all shots (the operators, geometry and maps are shared).  Each
@@ -180,17 +183,22 @@ dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, d
  * eager stepping. */
 dgh_status dgh_set_graph(dgh_ctx* ctx, int enable);
 
-/* Launch tuning of the 3D level.  Candidates (dgh_tuning_count: 4 for
- * N <= 4, else 2) are kernel * 2 + order: kernel 0 holds a whole tile on
- * chip (N <= 4; the only kernel for N = 5, 6), kernel 1 streams it through
- * registers; order 0 gives each of the 8 XCDs a contiguous range of
- * tiles, order 1 deals tiles round-robin over all workgroups.  Every
- * candidate computes the same step.  dgh_set_tuning forces a candidate;
- * dgh_autotune times `launches` launches (1..10000) of each on the bound
- * workload -- they read the current state and write only the other half of
- * its double buffer, so the state is unchanged -- keeps the fastest, returns
- * its index in *best and, if ms is not NULL, the milliseconds per launch of
- * every candidate in ms[0..count-1].  Both synchronise. */
+/* Launch tuning of the 3D level (the counterpart of the paper's choice of
+ * elements per block, Section 4.2).  Candidates (dgh_tuning_count: 12 for
+ * FP64 with N <= 4 and FP32 with N <= 5, else 6) are (kernel * 2 + order)
+ * * 3 + grid: kernel 0 holds a whole tile on chip where it fits (else it
+ * is the one kernel there is: register streaming, and for the BF16 variant
+ * its own kernel), kernel 1 streams it through registers; order 0 gives
+ * each of the 8 XCDs a contiguous range of tiles, order 1 deals tiles
+ * round-robin over all workgroups; grid 0, 1, 2 launches 8, 6 or 4 eighths
+ * of the workgroups that fit on the device at once, each walking more
+ * tiles when there are fewer.  Every candidate computes the same step.
+ * dgh_set_tuning forces a candidate; dgh_autotune times `launches`
+ * launches (1..10000) of each on the bound workload -- they read the
+ * current state and write only the other half of its double buffer, so the
+ * state is unchanged -- keeps the fastest, returns its index in *best and,
+ * if ms is not NULL, the milliseconds per launch of every candidate in
+ * ms[0..count-1].  Both synchronise. */
 dgh_status dgh_tuning_count(dgh_ctx* ctx, int* count);
 dgh_status dgh_set_tuning(dgh_ctx* ctx, int candidate);
 dgh_status dgh_autotune(dgh_ctx* ctx, int launches, int* best, double* ms);
@@ -212,9 +220,11 @@ dgh_status dgh_check(dgh_ctx* ctx, int shot, double e_ref, double rel_tol, doubl
 /* ---- Learned boundary closure (an extension beside the method: a small
  * MLP stands in for the order-P auxiliary recursion of Sections 2-3 on the
  * absorbing faces).  Network: 10 inputs (p and Z |u_t| of the 3D trace at a
- * face node, u_t the velocity tangential to the face, now and at the 4
- * previous step ends; divided by their root mean square, times in_scale)
- * -> 64 -> 64 -> 64 (tanh) -> y; r- = g_max tanh(y) r+ with r+ =
+ * face node, u_t the velocity tangential to the face, at the current step
+ * end, then the root mean squares of p and of Z |u_t| over the recent past
+ * at the four time scales of dgh_set_closure_memory -- exponential averages
+ * of their squares updated at every step end; all divided by their root
+ * mean square, times in_scale) -> 64 -> 64 -> 64 (tanh) -> y; r- = g_max tanh(y) r+ with r+ =
  * (p + Z n.u)/2 the current outgoing characteristic, so |r-| <= |g_max|
  * |r+| at every node and the closed loop cannot gain energy at the
  * boundary.  A sample row is the 10 raw inputs followed by r+.  Parameters (FP32,
@@ -226,14 +236,23 @@ dgh_status dgh_check(dgh_ctx* ctx, int shot, double e_ref, double rel_tol, doubl
  * n_w = 0 returns to the plain method.  Needs P = 0 (no auxiliary fields)
  * and |g_max| <= 1 (DGH_EINVAL otherwise);
  * edges and corners then have no compatibility systems.  The network runs
- * once per step, at its end, on the traces of that step end and the 4
- * before it (the inputs dgh_closure_sample records); its r- then holds for
- * every stage of the next step.  dgh_set_state clears a shot's trace
- * history and its r- (qb3).  Waits for the work queued on the bound stream
- * before it writes the weights. */
+ * once per step, at its end, on the inputs of that step end (those
+ * dgh_closure_sample records); its r- then holds for every stage of the
+ * next step.  dgh_set_state clears a shot's trace memory and its r- (qb3).
+ * Waits for the work queued on the bound stream before it writes the
+ * weights. */
 dgh_status dgh_set_closure(dgh_ctx* ctx, const float* w, int n_w);
 
-/* Keeps the per-node trace history up to date at every step end (always on
+/* Time scales tau[DGH_CLOSURE_MEMORY] (> 0, time units of the problem) of
+ * the closure's averaged inputs: at a step end of length dt each average
+ * keeps exp(-dt/tau_k) of its value and takes the rest from the new
+ * square.  NULL restores the default 1.25, 2.5, 5 and 10 times h / c_max,
+ * h = (6 |Omega| / K)^(1/3) (the cell size of a Kuhn mesh).  Training data
+ * and use must share them. */
+#define DGH_CLOSURE_MEMORY 4
+dgh_status dgh_set_closure_memory(dgh_ctx* ctx, const double* tau);
+
+/* Keeps the per-node trace memory up to date at every step end (always on
  * while a closure is set), so that dgh_closure_sample can read it. */
 dgh_status dgh_closure_record(dgh_ctx* ctx, int enable);
 

@@ -51,11 +51,12 @@ def pade_f2(X, P, gamma=None):
                                  for n in range(P))
 
 
-def reflection_coefficient(theta, P):
+def reflection_coefficient(theta, P, gamma=None):
     """Plane-wave reflection of the planar condition (Section 2.1): for a wave
     hitting x = L at angle theta the symbol of the boundary operator gives
-    R = (cos(theta) - f_P(-sin^2 theta)) / (cos(theta) + f_P(-sin^2 theta))."""
-    f = pade_f2(-np.sin(theta) ** 2, P)
+    R = (cos(theta) - f_P(-sin^2 theta)) / (cos(theta) + f_P(-sin^2 theta)),
+    with the Pade coefficients or the given ones in the second form."""
+    f = pade_f2(-np.sin(theta) ** 2, P, gamma)
     return (np.cos(theta) - f) / (np.cos(theta) + f)
 
 

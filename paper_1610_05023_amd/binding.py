@@ -49,6 +49,7 @@ _SIGS = {
     "dgh_check": [C.c_void_p, C.c_int, C.c_double, C.c_double, C.POINTER(C.c_double)],
     "dgh_set_closure": [C.c_void_p, C.c_void_p, C.c_int],
     "dgh_closure_record": [C.c_void_p, C.c_int],
+    "dgh_set_closure_memory": [C.c_void_p, C.c_void_p],
     "dgh_closure_sample": [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p],
     "dgh_mlp_work_size": [C.c_int, C.POINTER(C.c_size_t)],
     "dgh_mlp_forward": [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p],
@@ -108,6 +109,7 @@ class Solver:
             raise DghError(f"dgh_create failed: {STATUS.get(st, st)}")
         self.h = h
         self.device = device
+        self.precision = precision
         VX = np.ascontiguousarray(VX, dtype=np.float64)
         EToV = np.ascontiguousarray(EToV, dtype=np.int32)
         if box is None:
@@ -255,6 +257,14 @@ class Solver:
 
     def closure_record(self, enable=True):
         self._call("dgh_closure_record", 1 if enable else 0)
+
+    def set_closure_memory(self, tau=None):
+        """Time scales of the closure's averaged inputs (4 values), or None
+        for the library's default."""
+        t = None if tau is None else np.ascontiguousarray(tau, dtype=np.float64)
+        if t is not None and t.size != 4:
+            raise ValueError("4 time scales")
+        self._call("dgh_set_closure_memory", _ptr(t))
 
     def closure_sample(self, shot=0):
         """(X[nodes][11], Y[nodes]) from the current state (float32): sample

@@ -4,14 +4,18 @@
 // Sections 2-3 produces), with hand-written training kernels.
 //
 // Inputs: p and Z |u_t| (u_t the velocity tangential to the face) at the
-// node now and at the 4 previous step ends, 10 values, divided by their own
-// root mean square (a linear boundary's reflection gain does not depend on
-// the amplitude) and times in_scale.  For a plane wave, p and Z |u_t| carry
-// the same factor whatever part of it the boundary reflects, so their ratio
-// (sin of the incidence angle) does not feed back on the closure's own
-// output; Z n.u is left out on purpose, as it would let the network copy
-// the interior's incoming characteristic, a map that in the continuum
-// imposes no condition at all.
+// node now, and the root mean squares of p and of Z |u_t| over the recent
+// past at four time scales tau_1..tau_4 (exponential averages of their
+// squares, updated at every step end with the weight 1 - exp(-dt/tau_k) of
+// the new value), 10 values, divided by their own root mean square (a
+// linear boundary's reflection gain does not depend on the amplitude) and
+// times in_scale.  For a plane wave, p and Z |u_t| carry the same factor
+// whatever part of it the boundary reflects, so their ratio (sin of the
+// incidence angle) does not feed back on the closure's own output, and the
+// averages over a fixed physical time keep that ratio where p itself
+// passes through zero; Z n.u is left out on purpose, as it would let the
+// network copy the interior's incoming characteristic, a map that in the
+// continuum imposes no condition at all.
 // Network (FP32): 10 -> 64 -> 64 -> 64 (tanh) -> y, and r- = g_max tanh(y)
 // r+ with r+ = (p + Z n.u)/2 the current outgoing characteristic.  The
 // network thus picks a reflection gain in (-g_max, g_max); with g_max <= 1
@@ -42,8 +46,29 @@ constexpr int oW1 = 2, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH
               oW3 = ob2 + kH, ob3 = oW3 + kH * kH, oW4 = ob3 + kH, ob4 = oW4 + kH;
 constexpr int kNW = ob4 + 1;        // 9091
 constexpr int kThreads = 256;
-constexpr int kHist = 10;           // history per node: (p, Z |u_t|) at 5 step ends
-static_assert(kHist == kIn, "the closure reads the whole history as its inputs");
+// memory per node: p, Z |u_t| at the last step end, then the averages of
+// p^2 and (Z |u_t|)^2 at the four time scales
+constexpr int kHist = 10;
+static_assert(kHist == kIn, "one input per memory value");
+static_assert(kHist == 2 + 2 * kMemScales, "memory layout");
+
+// Updates a node's memory h[kHist] with the traces p, zut of a step end
+// and writes the inputs f[kIn]: p, zut and the square roots of the averages.
+__device__ __forceinline__ void memory_update(float* h, float p, float zut, const Memory& mem,
+                                              float* f) {
+  h[0] = p;
+  h[1] = zut;
+  f[0] = p;
+  f[1] = zut;
+#pragma unroll
+  for (int k = 0; k < kMemScales; ++k) {
+    const float a = mem.decay[k];
+    h[2 + 2 * k] = a * h[2 + 2 * k] + (1.f - a) * p * p;
+    h[3 + 2 * k] = a * h[3 + 2 * k] + (1.f - a) * zut * zut;
+    f[2 + 2 * k] = sqrtf(h[2 + 2 * k]);
+    f[3 + 2 * k] = sqrtf(h[3 + 2 * k]);
+  }
+}
 static_assert(kNW == kMlpParams, "parameter layout");
 
 // 1 / root mean square of the raw inputs (0 inputs stay 0)
@@ -285,7 +310,8 @@ __global__ void __launch_bounds__(kCW * 64) k_closure(Lvl2 L2, const float* __re
                                                       const T3* __restrict__ q3, int np3,
                                                       float* __restrict__ hist,
                                                       double* __restrict__ qb3,
-                                                      double* __restrict__ q03, Shots sh) {
+                                                      double* __restrict__ q03, Shots sh,
+                                                      Memory mem) {
   __shared__ float cw[kCF];
   __shared__ float tl[kCW][kH * 16];        // per wave: a hidden layer, [row][node]
   // weights in fragment order
@@ -329,14 +355,15 @@ __global__ void __launch_bounds__(kCW * 64) k_closure(Lvl2 L2, const float* __re
   const bool valid = x < nn;
   const int xc = valid ? x : nn - 1;
   const int t = xc / L2.Np, a = xc - t * L2.Np;
-  float f[kHist], zun;
-  node_trace(L2, q3, np3, t, a, f[0], zun, f[1]);
+  float f[kIn], h[kHist], p, zun, zut;
+  node_trace(L2, q3, np3, t, a, p, zun, zut);
 #pragma unroll
-  for (int j = 0; j < kHist - 2; ++j) f[2 + j] = hist[(size_t)xc * kHist + j];
+  for (int j = 0; j < kHist; ++j) h[j] = hist[(size_t)xc * kHist + j];
+  memory_update(h, p, zut, mem, f);
   if (valid && q == 0) {
     float* o = hist + (size_t)x * kHist;
 #pragma unroll
-    for (int j = 0; j < kHist; ++j) o[j] = f[j];
+    for (int j = 0; j < kHist; ++j) o[j] = h[j];
   }
   const float inv = input_inv_rms(f);
   float* T = tl[wv];
@@ -399,12 +426,12 @@ __global__ void __launch_bounds__(kCW * 64) k_closure(Lvl2 L2, const float* __re
   }
 }
 
-// End of a step: the history (5 step ends, most recent first) moves one
-// step back and takes the current traces as its most recent entry.
+// End of a step: every node's memory takes the current traces (as
+// k_closure does before it evaluates the network).
 template <class T3>
 __global__ void __launch_bounds__(kThreads) k_hist_push(Lvl2 L2, const T3* __restrict__ q3,
                                                         int np3, float* __restrict__ hist,
-                                                        Shots sh) {
+                                                        Shots sh, Memory mem) {
   const size_t k = blockIdx.y;
   q3 += k * sh.st3;
   const int nn = L2.Kt * L2.Np;
@@ -414,20 +441,20 @@ __global__ void __launch_bounds__(kThreads) k_hist_push(Lvl2 L2, const T3* __res
   const int t = x / L2.Np, a = x - t * L2.Np;
   float p, zun, zut;
   node_trace(L2, q3, np3, t, a, p, zun, zut);
-  float h[kHist];
+  float h[kHist], f[kIn];
 #pragma unroll
   for (int j = 0; j < kHist; ++j) h[j] = hist[(size_t)x * kHist + j];
+  memory_update(h, p, zut, mem, f);
   float* o = hist + (size_t)x * kHist;
-  o[0] = p;
-  o[1] = zut;
 #pragma unroll
-  for (int j = 2; j < kHist; ++j) o[j] = h[j - 2];
+  for (int j = 0; j < kHist; ++j) o[j] = h[j];
 }
 
 // Training samples of one shot, taken after a step end (whose traces the
-// history already holds first): X[node][11] = the raw inputs (the current
-// p, Z |u_t| and the 4 step ends before them) and r+, Y[node] = the current
-// qb3 -- the r- the face rule produced at the step's last stage.
+// memory already holds): X[node][11] = the raw inputs (the current p,
+// Z |u_t| and the root mean squares at the four time scales) and r+,
+// Y[node] = the current qb3 -- the r- the face rule produced at the step's
+// last stage.
 template <class T3>
 __global__ void __launch_bounds__(kThreads) k_closure_sample(Lvl2 L2, const T3* __restrict__ q3,
                                                              int np3, const float* __restrict__ hist,
@@ -444,7 +471,7 @@ __global__ void __launch_bounds__(kThreads) k_closure_sample(Lvl2 L2, const T3* 
   r[0] = p;
   r[1] = zut;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) r[2 + j] = hist[(size_t)x * kHist + 2 + j];
+  for (int j = 0; j < 8; ++j) r[2 + j] = sqrtf(hist[(size_t)x * kHist + 2 + j]);
   r[kIn] = 0.5f * (p + zun);
   Y[x] = (float)qb3[x];
 }
@@ -530,7 +557,7 @@ const float* mlp_loss_partials(const float* work, int n) {
 
 hipError_t launch_closure(const Lvl2& L2, const float* W, const void* q3, int q3f32, int np3,
                           float* hist, double* qb3, double* q03, const Shots& sh,
-                          hipStream_t st) {
+                          const Memory& mem, hipStream_t st) {
   const int nn = L2.Kt * L2.Np;
   if (nn == 0) return hipSuccess;
   const int tiles = (nn + 15) / 16;
@@ -544,24 +571,24 @@ hipError_t launch_closure(const Lvl2& L2, const float* W, const void* q3, int q3
   const dim3 g(std::min((tiles + kCW - 1) / kCW, per_shot), sh.n), b(kCW * 64);
   if (q3f32)
     hipLaunchKernelGGL(k_closure<float>, g, b, 0, st, L2, W, static_cast<const float*>(q3), np3,
-                       hist, qb3, q03, sh);
+                       hist, qb3, q03, sh, mem);
   else
     hipLaunchKernelGGL(k_closure<double>, g, b, 0, st, L2, W, static_cast<const double*>(q3), np3,
-                       hist, qb3, q03, sh);
+                       hist, qb3, q03, sh, mem);
   return hipGetLastError();
 }
 
 hipError_t launch_hist_push(const Lvl2& L2, const void* q3, int q3f32, int np3, float* hist,
-                            const Shots& sh, hipStream_t st) {
+                            const Shots& sh, const Memory& mem, hipStream_t st) {
   const int nn = L2.Kt * L2.Np;
   if (nn == 0) return hipSuccess;
   const dim3 g((nn + kThreads - 1) / kThreads, sh.n), b(kThreads);
   if (q3f32)
     hipLaunchKernelGGL(k_hist_push<float>, g, b, 0, st, L2, static_cast<const float*>(q3), np3,
-                       hist, sh);
+                       hist, sh, mem);
   else
     hipLaunchKernelGGL(k_hist_push<double>, g, b, 0, st, L2, static_cast<const double*>(q3), np3,
-                       hist, sh);
+                       hist, sh, mem);
   return hipGetLastError();
 }
 

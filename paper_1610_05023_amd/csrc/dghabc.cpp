@@ -34,7 +34,7 @@ struct Region {
 
 struct Layout {
   size_t total = 0;
-  Region q3[2], res3, geo3, zn3, nbr3, ops3, ops3f, fmask3, fmap3, mass3, J3, esum;
+  Region q3[2], res3, geo3, zn3, nbr3, ops3, ops3f, ops3b, fmask3, fmap3, mass3, J3, esum;
   Region q2[2], res2, qb3, q03, geo2, edge2, info2, tetnode2, nbrnode2, ops2, fmask2, gamma;
   Region q1[2], res1, qb2, q02, geo1, info1, trinode1, ops1, cji, cij, G, H;
   Region qb1, info0, nrm0, T, srcw, srcp, flags, ops2f;
@@ -84,6 +84,7 @@ struct dgh_ctx {
   dgh::Lvl0 L0{};
   bool closure = false;               // learned closure replaces the face level
   bool record = false;                // keep the trace history for sampling
+  double mem_tau[dgh::kMemScales] = {0, 0, 0, 0};   // closure time scales (0: default)
   dgh::LvlF LF{};
   // replayed stepping: one captured step per starting buffer parity, valid
   // for (gdt, gclosure, grecord); captured on a stream of the library's own
@@ -141,6 +142,7 @@ hipError_t dzero(dgh_ctx* c, void* dst, size_t bytes) {
 struct HostArrays {
   std::vector<double> geo3, zn3, ops3, mass3, J3, ops2f;
   std::vector<float> ops3f;
+  std::vector<unsigned short> ops3b;
   std::vector<int> nbr3, fmask3, fmap3;
   std::vector<double> geo2, edge2, ops2;
   std::vector<int> info2, tetnode2, nbrnode2, fmask2;
@@ -258,6 +260,40 @@ void build_host_arrays(dgh_ctx* c, HostArrays& h) {
               h.ops3f[off + (((size_t)rb * 4 + f) * FK + jj) * 64 + l] =
                   (float)m.tet.LIFT[row * 4 * Nfp + f * Nfp + k];
           }
+  }
+  if (c->precision == DGH_BF16_MFMA) {
+    // A-fragments of the BF16 16x16x16 MFMA (see Lvl3::opsb): operator
+    // entries rounded to FP32, then to the nearest BF16 (ties to even)
+    const int RB = (Np + 15) / 16, FK = (Nfp + 15) / 16;
+    h.ops3b.assign(dgh::frag3b_size(m.N), 0);
+    auto bf16 = [](double v) {
+      const float f = (float)v;
+      unsigned u;
+      std::memcpy(&u, &f, 4);
+      return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    };
+    const dgh::Mat* Ds[3] = {&m.tet.Dr, &m.tet.Ds, &m.tet.Dt};
+    for (int d = 0; d < 3; ++d)
+      for (int rb = 0; rb < RB; ++rb)
+        for (int j = 0; j < RB; ++j)
+          for (int l = 0; l < 64; ++l)
+            for (int i = 0; i < 4; ++i) {
+              const int row = 16 * rb + l % 16, col = 16 * j + 4 * (l / 16) + i;
+              if (row < Np && col < Np)
+                h.ops3b[((((size_t)d * RB + rb) * RB + j) * 64 + l) * 4 + i] =
+                    bf16((*Ds[d])[row * Np + col]);
+            }
+    const size_t off = (size_t)3 * RB * RB * 64 * 4;
+    for (int rb = 0; rb < RB; ++rb)
+      for (int f = 0; f < 4; ++f)
+        for (int jj = 0; jj < FK; ++jj)
+          for (int l = 0; l < 64; ++l)
+            for (int i = 0; i < 4; ++i) {
+              const int row = 16 * rb + l % 16, k = 16 * jj + 4 * (l / 16) + i;
+              if (row < Np && k < Nfp)
+                h.ops3b[off + ((((size_t)rb * 4 + f) * FK + jj) * 64 + l) * 4 + i] =
+                    bf16(m.tet.LIFT[row * 4 * Nfp + f * Nfp + k]);
+            }
   }
   h.mass3 = m.tet.Mass;
   h.fmask3 = m.tet.Fmask;
@@ -417,7 +453,7 @@ void compute_layout(dgh_ctx* c) {
   const size_t d = sizeof(double), i4 = sizeof(int), S = (size_t)c->n_shots;
   // every state array holds n_shots shots, each starting 256-byte aligned
   const int Kt = m.Ktri, Np2 = m.tri.Np, Nfp2 = m.tri.Nfp, Kl = m.Klin, Np1 = m.line.Np;
-  L.e3 = c->precision == DGH_FP32_MFMA ? 4 : 8;
+  L.e3 = c->precision == DGH_FP64 ? 8 : 4;   // FP32 state in both mixed forms
   L.st3 = ((size_t)nt * 4 * Np * T + 63) / 64 * 64;   // 256-byte aligned shots
   // at least one set of one triangle (read, unused, by the face kernel at P = 0)
   L.st2 = round32((size_t)Kt * std::max(P, 1) * 3 * Np2);
@@ -434,6 +470,7 @@ void compute_layout(dgh_ctx* c) {
   L.add(L.nbr3, (size_t)nt * 4 * T * i4);
   L.add(L.ops3, (size_t)dgh::frag3_size(m.N) * d);
   L.add(L.ops3f, L.e3 == 4 ? (size_t)dgh::frag3f_size(m.N) * sizeof(float) : 1);
+  L.add(L.ops3b, c->precision == DGH_BF16_MFMA ? (size_t)dgh::frag3b_size(m.N) * 2 : 1);
   L.add(L.fmask3, (size_t)4 * Nfp * i4);
   L.add(L.fmap3, (size_t)96 * Nfp * i4);
   L.add(L.mass3, (size_t)Np * Np * d);
@@ -495,12 +532,14 @@ void fill_levels(dgh_ctx* c) {
   dgh::Lvl3& a = c->L3;
   a.K = m.K;
   a.ntile = c->ntile;
+  if (a.eighths == 0) a.eighths = 8;   // the whole resident grid unless tuned
   a.N = m.N;
   a.Np = m.tet.Np;
   a.Nfp = m.tet.Nfp;
   a.nqb3 = std::max(m.tet.Nfp, m.Ktri * m.tri.Np);
   a.ops = dptr<double>(c, L.ops3);
   a.ops32 = dptr<float>(c, L.ops3f);
+  a.opsb = dptr<unsigned short>(c, L.ops3b);
   a.fmask = dptr<int>(c, L.fmask3);
   a.fmap = dptr<int>(c, L.fmap3);
   a.geo = dptr<double>(c, L.geo3);
@@ -576,7 +615,8 @@ extern "C" {
 dgh_status dgh_create(dgh_ctx** out, int device, int precision, int n_shots) {
   if (!out) return DGH_EINVAL;
   *out = nullptr;
-  if ((precision != DGH_FP64 && precision != DGH_FP32_MFMA) || n_shots < 1 || n_shots > 4096 ||
+  if ((precision != DGH_FP64 && precision != DGH_FP32_MFMA && precision != DGH_BF16_MFMA) ||
+      n_shots < 1 || n_shots > 4096 ||
       device < 0)
     return DGH_EINVAL;
   dgh_ctx* c = new (std::nothrow) dgh_ctx();
@@ -721,6 +761,7 @@ dgh_status dgh_bind_workspace(dgh_ctx* c, void* dev, size_t bytes, void* stream)
   HIPCHECK(c, upload(c, L.nbr3, h.nbr3));
   HIPCHECK(c, upload(c, L.ops3, h.ops3));
   HIPCHECK(c, upload(c, L.ops3f, h.ops3f));
+  HIPCHECK(c, upload(c, L.ops3b, h.ops3b));
   HIPCHECK(c, upload(c, L.fmask3, h.fmask3));
   HIPCHECK(c, upload(c, L.fmap3, h.fmap3));
   HIPCHECK(c, upload(c, L.mass3, h.mass3));
@@ -912,6 +953,36 @@ dgh_status dgh_set_source(dgh_ctx* c, int shot, const double* xs, double f0, dou
 
 namespace {
 
+// The 3D level of one stage in the context's arithmetic: reads q3[o],
+// writes q3[n] and the residual `res` (which may alias q3[n] when timing).
+hipError_t launch3d(dgh_ctx* c, int o, int n, const Region& res, double A, double B, double dt,
+                    const dgh::Shots& sh, hipStream_t st) {
+  const Layout& L = c->lay;
+  if (c->precision == DGH_BF16_MFMA)
+    return dgh::launch_level3_bf16(c->L3, dptr<float>(c, L.q3[o]), dptr<float>(c, L.q3[n]),
+                                   dptr<float>(c, res), dptr<double>(c, L.qb3), A, B, dt, sh, st);
+  if (c->precision == DGH_FP32_MFMA)
+    return dgh::launch_level3_f32(c->L3, dptr<float>(c, L.q3[o]), dptr<float>(c, L.q3[n]),
+                                  dptr<float>(c, res), dptr<double>(c, L.qb3), A, B, dt, sh, st);
+  return dgh::launch_level3(c->L3, dptr<double>(c, L.q3[o]), dptr<double>(c, L.q3[n]),
+                            dptr<double>(c, res), dptr<double>(c, L.qb3), A, B, dt, sh, st);
+}
+
+// The closure's time scales: as set, or by default 1.25, 2.5, 5 and 10
+// times h / c_max, with h = (6 |Omega| / K)^(1/3) the edge of a cube cell of
+// the mesh's mean element volume (the Kuhn cell size).
+const double* memory_tau(dgh_ctx* c) {
+  if (c->mem_tau[0] > 0.0) return c->mem_tau;
+  static thread_local double tau[dgh::kMemScales];
+  const dgh::Mesh& m = c->mesh;
+  double vol = 0.0, cmax = 0.0;
+  for (int e = 0; e < m.K; ++e) vol += m.J[e] * (4.0 / 3.0);
+  for (double v : c->c) cmax = std::max(cmax, v);
+  const double h = std::cbrt(6.0 * vol / std::max(1, m.K));
+  for (int k = 0; k < dgh::kMemScales; ++k) tau[k] = 1.25 * (double)(1 << k) * h / cmax;
+  return tau;
+}
+
 // One step (5 stages, Algorithm 1 order) on `st`.  Eager: the stage times
 // come from t; replayed (clk non-null): from the device clock, which the
 // step advances at its end.
@@ -934,14 +1005,7 @@ dgh_status enqueue_step(dgh_ctx* c, double dt, double t, hipStream_t st, double*
       }
       HIPCHECK(c, hipEventRecord(c->ev[c->ev_used], st));
     }
-    if (L.e3 == 4)
-      HIPCHECK(c, dgh::launch_level3_f32(c->L3, dptr<float>(c, L.q3[o]), dptr<float>(c, L.q3[n]),
-                                         dptr<float>(c, L.res3), dptr<double>(c, L.qb3), kA[s],
-                                         kB[s], dt, sh, st));
-    else
-      HIPCHECK(c, dgh::launch_level3(c->L3, dptr<double>(c, L.q3[o]), dptr<double>(c, L.q3[n]),
-                                     dptr<double>(c, L.res3), dptr<double>(c, L.qb3), kA[s],
-                                     kB[s], dt, sh, st));
+    HIPCHECK(c, launch3d(c, o, n, L.res3, kA[s], kB[s], dt, sh, st));
     if (timed) {
       HIPCHECK(c, hipEventRecord(c->ev[c->ev_used + 1], st));
       c->ev_used += 2;
@@ -962,13 +1026,19 @@ dgh_status enqueue_step(dgh_ctx* c, double dt, double t, hipStream_t st, double*
                                      dptr<double>(c, L.q02), kA[s], kB[s], dt, sh, st));
     c->cur = n;
   }
-  if (c->closure)
-    HIPCHECK(c, dgh::launch_closure(c->L2, dptr<float>(c, L.mlpw), c->ws + L.q3[c->cur].off,
-                                    L.e3 == 4 ? 1 : 0, c->mesh.tet.Np, dptr<float>(c, L.hist),
-                                    dptr<double>(c, L.qb3), dptr<double>(c, L.q03), sh, st));
-  else if (c->record)
-    HIPCHECK(c, dgh::launch_hist_push(c->L2, c->ws + L.q3[c->cur].off, L.e3 == 4 ? 1 : 0,
-                                      c->mesh.tet.Np, dptr<float>(c, L.hist), sh, st));
+  if (c->closure || c->record) {
+    dgh::Memory mem;
+    const double* tau = memory_tau(c);
+    for (int k = 0; k < dgh::kMemScales; ++k) mem.decay[k] = (float)std::exp(-dt / tau[k]);
+    if (c->closure)
+      HIPCHECK(c, dgh::launch_closure(c->L2, dptr<float>(c, L.mlpw), c->ws + L.q3[c->cur].off,
+                                      L.e3 == 4 ? 1 : 0, c->mesh.tet.Np, dptr<float>(c, L.hist),
+                                      dptr<double>(c, L.qb3), dptr<double>(c, L.q03), sh, mem,
+                                      st));
+    else
+      HIPCHECK(c, dgh::launch_hist_push(c->L2, c->ws + L.q3[c->cur].off, L.e3 == 4 ? 1 : 0,
+                                        c->mesh.tet.Np, dptr<float>(c, L.hist), sh, mem, st));
+  }
   if (clk) HIPCHECK(c, dgh::launch_clock_tick(clk, st));
   return DGH_OK;
 }
@@ -1051,9 +1121,20 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
 }
 
 namespace {
-// tuning candidates: N <= 4 has two 3D kernels x two item orders, N = 5, 6
-// one kernel x two item orders; candidate = kernel * 2 + order
-int tuning_count(const dgh_ctx* c) { return c->N <= 4 ? 4 : 2; }
+// tuning candidates: two 3D kernels (tile on chip, register streaming)
+// where the tile fits on chip (FP64 N <= 4, FP32 N <= 5), else one; x two
+// item orders; x three persistent grid sizes (8, 6 or 4 eighths of the
+// resident workgroups); candidate = (kernel * 2 + order) * 3 + grid
+constexpr int kGrids[3] = {8, 6, 4};
+int tuning_count(const dgh_ctx* c) {
+  const int nmax = c->precision == DGH_FP64 ? 4 : (c->precision == DGH_FP32_MFMA ? 5 : 0);
+  return (c->N <= nmax ? 4 : 2) * 3;
+}
+void apply_tuning(dgh_ctx* c, int candidate) {
+  c->L3.kvar = (candidate / 3) >> 1;
+  c->L3.order = (candidate / 3) & 1;
+  c->L3.eighths = kGrids[candidate % 3];
+}
 }  // namespace
 
 dgh_status dgh_tuning_count(dgh_ctx* c, int* count) {
@@ -1068,8 +1149,7 @@ dgh_status dgh_set_tuning(dgh_ctx* c, int candidate) {
   if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "tuning before bind");
   if (candidate < 0 || candidate >= tuning_count(c)) return fail(c, DGH_EINVAL, "no such candidate");
   HIPCHECK(c, hipStreamSynchronize(c->stream));
-  c->L3.kvar = candidate >> 1;
-  c->L3.order = candidate & 1;
+  apply_tuning(c, candidate);
   drop_graphs(c);   // captured launches carry the old choice
   return DGH_OK;
 }
@@ -1088,21 +1168,14 @@ dgh_status dgh_autotune(dgh_ctx* c, int launches, int* best, double* ms) {
   hipEvent_t e0, e1;
   HIPCHECK(c, hipEventCreate(&e0));
   HIPCHECK(c, hipEventCreate(&e1));
-  const int keep_kvar = c->L3.kvar, keep_order = c->L3.order;
+  const int keep_kvar = c->L3.kvar, keep_order = c->L3.order, keep_eighths = c->L3.eighths;
   double tbest = 0.0;
   int ibest = -1;
   hipError_t err = hipSuccess;
   for (int k = 0; k < nc && err == hipSuccess; ++k) {
-    c->L3.kvar = k >> 1;
-    c->L3.order = k & 1;
+    apply_tuning(c, k);
     auto launch = [&]() {
-      if (L.e3 == 4)
-        return dgh::launch_level3_f32(c->L3, dptr<float>(c, L.q3[cur]), dptr<float>(c, L.q3[1 - cur]),
-                                      dptr<float>(c, L.q3[1 - cur]), dptr<double>(c, L.qb3),
-                                      kA[0], kB[0], 1e-6, sh, c->stream);
-      return dgh::launch_level3(c->L3, dptr<double>(c, L.q3[cur]), dptr<double>(c, L.q3[1 - cur]),
-                                dptr<double>(c, L.q3[1 - cur]), dptr<double>(c, L.qb3), kA[0],
-                                kB[0], 1e-6, sh, c->stream);
+      return launch3d(c, cur, 1 - cur, L.q3[1 - cur], kA[0], kB[0], 1e-6, sh, c->stream);
     };
     for (int w = 0; w < 2 && err == hipSuccess; ++w) err = launch();
     if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
@@ -1125,10 +1198,10 @@ dgh_status dgh_autotune(dgh_ctx* c, int launches, int* best, double* ms) {
   if (err != hipSuccess) {
     c->L3.kvar = keep_kvar;
     c->L3.order = keep_order;
+    c->L3.eighths = keep_eighths;
     return hipfail(c, err, "autotune");
   }
-  c->L3.kvar = ibest >> 1;
-  c->L3.order = ibest & 1;
+  apply_tuning(c, ibest);
   drop_graphs(c);
   *best = ibest;
   return DGH_OK;
@@ -1144,8 +1217,9 @@ dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, d
     if (c->stage < S_BOUND) return fail(c0, DGH_ESTATE, "group member not bound");
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return fail(c0, DGH_EINVAL, "a context appears twice in the group");
-    if (c->N > 4 || c->L3.kvar != 0)
-      return fail(c0, DGH_EINVAL, "group steps need N <= 4 and the tile-on-chip kernel");
+    if (c->N > 4 || c->L3.kvar != 0 || c->precision == DGH_BF16_MFMA)
+      return fail(c0, DGH_EINVAL,
+                  "group steps need N <= 4, FP64 or FP32 and the tile-on-chip kernel");
     if (c->N != c0->N || c->lay.e3 != c0->lay.e3 || c->device != c0->device ||
         c->stream != c0->stream)
       return fail(c0, DGH_EINVAL, "group members need the same N, precision, device and stream");
@@ -1311,6 +1385,19 @@ dgh_status dgh_set_closure(dgh_ctx* c, const float* w, int n_w) {
   HIPCHECK(c, hipStreamSynchronize(c->stream));   // no step still reads the weights
   HIPCHECK(c, h2d(c, c->ws + c->lay.mlpw.off, w, (size_t)n_w * sizeof(float)));
   c->closure = true;
+  return DGH_OK;
+}
+
+dgh_status dgh_set_closure_memory(dgh_ctx* c, const double* tau) {
+  if (!c) return DGH_EINVAL;
+  if (c->stage < S_BOUND) return fail(c, DGH_ESTATE, "set_closure_memory before bind");
+  if (tau)
+    for (int k = 0; k < dgh::kMemScales; ++k)
+      if (!(tau[k] > 0.0) || !std::isfinite(tau[k]))
+        return fail(c, DGH_EINVAL, "closure time scales must be positive and finite");
+  HIPCHECK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < dgh::kMemScales; ++k) c->mem_tau[k] = tau ? tau[k] : 0.0;
+  drop_graphs(c);   // captured launches carry the old decay factors
   return DGH_OK;
 }
 

@@ -15,6 +15,13 @@ inline int frag3f_size(int N) {
   return (3 * RB * RG + RB * 4 * FK) * 64;
 }
 
+// Number of BF16 values of the BF16 variant's fragments for degree N.
+inline int frag3b_size(int N) {
+  const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
+  const int RB = (Np + 15) / 16, FK = (Nfp + 15) / 16;
+  return (3 * RB * RB + RB * 4 * FK) * 64 * 4;
+}
+
 // Number of doubles of the 3D operator fragments for degree N.
 inline int frag3_size(int N) {
   const int Np = (N + 1) * (N + 2) * (N + 3) / 6, Nfp = (N + 1) * (N + 2) / 2;
@@ -42,6 +49,12 @@ struct Lvl3 {
   // LIFT as [RB][4][FK][64] with lane l holding LIFT[16 rb + l%16][f Nfp +
   // 4 jj + l/16]; zero outside the matrix.  RB = ceil(Np/16).
   const float* ops32;
+  // BF16 variant: A-fragments of the BF16 16x16x16 MFMA, Dr, Ds, Dt as
+  // [3][RB][RB][64] with lane l holding the four BF16 values D[16 rb + l%16]
+  // [16 j + 4 (l/16) + i], i = 0..3, then LIFT as [RB][4][FKB][64] with lane
+  // l holding LIFT[16 rb + l%16][f Nfp + 16 jj + 4 (l/16) + i]; zero outside
+  // the matrix.  FKB = ceil(Nfp/16).
+  const unsigned short* opsb;
   const int* fmask;    // 4 x Nfp
   const int* fmap;     // 4 x 4 x 6 x Nfp
   const double* geo;
@@ -49,7 +62,16 @@ struct Lvl3 {
   const int* nbr;
   int kvar;    // FP64 3D kernel for N <= 4: 0 tile on chip, 1 register-streaming
   int order;   // work items: 0 XCD-contiguous ranges, 1 round-robin over blocks
+  int eighths; // persistent grid: this many eighths of the resident workgroups
 };
+
+// Persistent grid of a 3D launch: the resident workgroups (fewer when there
+// are fewer items) times eighths/8, a multiple of 8 so that every XCD has
+// blocks for its range.
+inline int grid3(long long resident, long long items, int eighths) {
+  const long long b = (resident < items ? resident : items) * eighths / 8;
+  return (int)(b < 8 ? 8 : b / 8 * 8);
+}
 
 // 2D level (faces).  q2 [Ktri][P][3][Np2]; geo [Ktri][8]: rx ry sx sy 1/rho
 // rho*c^2 rho*c (pad); info [Ktri][8]: owning tet, axis of the domain face,
@@ -152,6 +174,9 @@ hipError_t launch_level3(const Lvl3& L, const double* qo, double* qn, double* re
 hipError_t launch_level3_f32(const Lvl3& L, const float* qo, float* qn, float* res,
                              const double* qb3, double A, double B, double dt, const Shots& sh,
                              hipStream_t st);
+hipError_t launch_level3_bf16(const Lvl3& L, const float* qo, float* qn, float* res,
+                              const double* qb3, double A, double B, double dt, const Shots& sh,
+                              hipStream_t st);
 // Work list of the line-group kernel: block b updates the lines
 // lines[b][*] (each with its edge system), then the corners corners[b][*];
 // -1 ends a list.  A block holds every line of its corners.
@@ -184,6 +209,13 @@ inline int frag2_size(int N) {
   return (2 * RG * RG + RG * 3 * EK) * 16;
 }
 
+// Learned closure (closure.hip): the decay per step exp(-dt/tau_k) of the
+// averages of p^2 and (Z |u_t|)^2 at the closure's time scales tau_k.
+constexpr int kMemScales = 4;
+struct Memory {
+  float decay[kMemScales];
+};
+
 // Learned closure (closure.hip): MLP parameters, flat, FP32.
 constexpr int kMlpParams = 9091;
 size_t mlp_work_floats(int n);
@@ -200,9 +232,9 @@ hipError_t mlp_adam(float* W, const float* G, float* M, float* V, int t, float l
                     float b2, float eps, hipStream_t st);
 hipError_t launch_closure(const Lvl2& L2, const float* W, const void* q3, int q3f32, int np3,
                           float* hist, double* qb3, double* q03, const Shots& sh,
-                          hipStream_t st);
+                          const Memory& mem, hipStream_t st);
 hipError_t launch_hist_push(const Lvl2& L2, const void* q3, int q3f32, int np3, float* hist,
-                            const Shots& sh, hipStream_t st);
+                            const Shots& sh, const Memory& mem, hipStream_t st);
 hipError_t launch_closure_sample(const Lvl2& L2, const void* q3, int q3f32, int np3,
                                  const float* hist, const double* qb3, float* X, float* Y,
                                  hipStream_t st);

@@ -34,7 +34,11 @@ struct Dims3f {
   static constexpr int RB = (Np + 15) / 16;   // row blocks of 16 nodes
   static constexpr int FK = (Nfp + 3) / 4;    // lifting k-steps per face
   static constexpr int NOPS = (3 * RB * RG + RB * 4 * FK) * 64;   // floats
-  static constexpr bool kLds = NOPS * 4 <= 64 * 1024;
+  // operator fragments in LDS up to 150 KB (N <= 6); above 64 KB the
+  // register-streaming kernel runs one workgroup per CU, with 512 registers
+  // per wave
+  static constexpr bool kLds = NOPS * 4 <= 150 * 1024;
+  static constexpr int kOcc = NOPS * 4 <= 64 * 1024 ? 2 : 1;
 };
 
 __device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
@@ -102,7 +106,7 @@ __device__ __forceinline__ void tile_f32(const Lvl3& L, const float* __restrict_
   f4 dpr[RB], dps[RB], dpt[RB], dv[RB];
 #pragma unroll
   for (int b = 0; b < RB; ++b) dpr[b] = dps[b] = dpt[b] = dv[b] = f4{0, 0, 0, 0};
-  constexpr int PF = N <= 4 ? 3 : 1;   // fewer registers left at N > 4
+  constexpr int PF = (N <= 4 || D::kOcc == 1) ? 3 : 1;   // k-steps of loads in flight
   float bp[PF], bu[PF], bv[PF], bw[PF];
 #pragma unroll
   for (int k = 0; k < PF; ++k) {
@@ -264,7 +268,7 @@ __device__ __forceinline__ void tile_f32(const Lvl3& L, const float* __restrict_
 }
 
 template <int N>
-__global__ void __launch_bounds__(kWaves3f * 64, 2) k_level3_f32(Lvl3 L, const float* __restrict__ qo,
+__global__ void __launch_bounds__(kWaves3f * 64, Dims3f<N>::kOcc) k_level3_f32(Lvl3 L, const float* __restrict__ qo,
                                                         float* __restrict__ qn,
                                                         float* __restrict__ res,
                                                         const double* __restrict__ qb3, float A,
@@ -287,7 +291,7 @@ __global__ void __launch_bounds__(kWaves3f * 64, 2) k_level3_f32(Lvl3 L, const f
 }
 
 // ------------------------------------------------- FP32, tile on chip ---
-// N <= 4: one workgroup of four waves per CU (one per SIMD).  Each wave's
+// N <= 5: one workgroup of four waves per CU (one per SIMD).  Each wave's
 // LDS buffer receives its next tile (FP32 state, geometry, impedances, face
 // codes) by direct buffer-to-LDS loads, issued once the current tile's copy
 // has been read for the last time (before the last face), so every value
@@ -729,7 +733,7 @@ hipError_t launch3f_dma(const Lvl3& L, const float* qo, float* qn, float* res, c
     if (e != hipSuccess) return e;
   }
   const long long items = (long long)ngrp * sh.n;
-  const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, items) / 8 * 8);
+  const int blocks = grid3(resident, items, L.eighths);
   hipLaunchKernelGGL(k_level3_f32_dma<N>, dim3(blocks), dim3(kWavesF * 64), lds, st, L, qo, qn,
                      res, qb3, (float)A, (float)B, (float)dt, sh);
   return hipGetLastError();
@@ -738,7 +742,7 @@ hipError_t launch3f_dma(const Lvl3& L, const float* qo, float* qn, float* res, c
 template <int N>
 hipError_t launch3f(const Lvl3& L, const float* qo, float* qn, float* res, const double* qb3,
                     double A, double B, double dt, const Shots& sh, hipStream_t st) {
-  if constexpr (N <= 4) {
+  if constexpr (N <= 5) {   // the tile buffers and fragments fit the LDS up to N = 5
     if (L.kvar == 0) return launch3f_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, st);
   }
   using D = Dims3f<N>;
@@ -753,8 +757,288 @@ hipError_t launch3f(const Lvl3& L, const float* qo, float* qn, float* res, const
     if (e != hipSuccess) return e;
   }
   const long long items = (long long)ngrp * sh.n;
-  const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, items) / 8 * 8);
+  const int blocks = grid3(resident, items, L.eighths);
   hipLaunchKernelGGL(k_level3_f32<N>, dim3(blocks), dim3(kWaves3f * 64), lds, st, L, qo, qn, res,
+                     qb3, (float)A, (float)B, (float)dt, sh);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ BF16 contractions ---
+// The FP32-state kernel with the volume and LIFT contractions on the BF16
+// 16x16x16 MFMA (FP32 accumulation): the operator fragments are BF16 (from
+// the host), the field values and fluxes are rounded to BF16 as they enter
+// an instruction; the state, the residual, the fluxes and the update stay
+// FP32.  Per instruction (K = 16):
+//   A: lane l -> A[l%16][4 (l/16) + i], i = 0..3 (four BF16 in 8 bytes)
+//   B: lane l -> B[4 (l/16) + i][l%16]
+//   D: rows 4 (l/16) + r of column l%16 (as the FP32 instruction)
+// so a lane's B operand of k-step j is the nodes 16 j + 4 (l/16) + i of its
+// element, and its accumulator rows 16 b + 4 (l/16) + r.
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+template <int N>
+struct Dims3b {
+  static constexpr int Np = (N + 1) * (N + 2) * (N + 3) / 6;
+  static constexpr int Nfp = (N + 1) * (N + 2) / 2;
+  static constexpr int RB = (Np + 15) / 16;   // row blocks (and volume k-steps) of 16 nodes
+  static constexpr int FK = (Nfp + 15) / 16;  // lifting k-steps per face
+  static constexpr int NFR = 3 * RB * RB + RB * 4 * FK;   // fragments of 64 lanes x 8 bytes
+  static constexpr int kOcc = NFR * 512 <= 64 * 1024 ? 2 : 1;
+};
+
+__device__ __forceinline__ f4 mfma_bf16(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// FP32 -> BF16, round to nearest even (finite inputs)
+__device__ __forceinline__ short bf16_rn(float x) {
+  const unsigned u = __builtin_bit_cast(unsigned, x);
+  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ s4 pack4(const float* v) {
+  return s4{bf16_rn(v[0]), bf16_rn(v[1]), bf16_rn(v[2]), bf16_rn(v[3])};
+}
+
+template <int N>
+__device__ __forceinline__ void tile_bf16(const Lvl3& L, const float* __restrict__ qo,
+                                          float* __restrict__ qn, float* __restrict__ res,
+                                          const double* __restrict__ qb3, float A, float B,
+                                          float dt, const Shots& sh, long long item, int ngrp,
+                                          const int* smap, const int* smask, const s4* sops,
+                                          int lane) {
+  using D = Dims3b<N>;
+  constexpr int Np = D::Np, Nfp = D::Nfp, RB = D::RB, FK = D::FK;
+  constexpr unsigned FS = Np * kTile * 4;   // bytes between two fields of a tile
+  constexpr unsigned TS = 4 * FS;           // bytes per tile
+  const int shot = (int)(item / ngrp);
+  const int tile = (int)(item - (long long)shot * ngrp) * kWaves3f + (threadIdx.x >> 6);
+  if (tile >= L.ntile) return;
+  qo += shot * sh.st3;
+  qn += shot * sh.st3;
+  res += shot * sh.st3;
+  qb3 += shot * sh.stb3;
+  const int es = lane & 15, g = lane >> 4;
+  const s4* frag = sops + lane;
+  const s4* fragL = frag + 3 * RB * RB * 64;
+  const int e = tile * kTile + es;
+  const unsigned nbytes = (unsigned)L.ntile * TS;
+  const Rsrc Rq = rsrc(qo, nbytes), Rn = rsrc(qn, nbytes), Rr = rsrc(res, nbytes);
+  const unsigned tb = (unsigned)tile * TS + (unsigned)es * 4;   // this lane's element
+  const double* gt = L.geo + (size_t)tile * 12 * kTile + es;
+  const float rx = (float)gt[0 * kTile], ry = (float)gt[1 * kTile], rz = (float)gt[2 * kTile];
+  const float sx = (float)gt[3 * kTile], sy = (float)gt[4 * kTile], sz = (float)gt[5 * kTile];
+  const float tx = (float)gt[6 * kTile], ty = (float)gt[7 * kTile], tz = (float)gt[8 * kTile];
+  const float irho = (float)gt[9 * kTile], Kb = (float)gt[10 * kTile], Z = (float)gt[11 * kTile];
+  const int* nbrt = L.nbr + tile * 4 * kTile + es;
+  const double* znt = L.zn + tile * 4 * kTile + es;
+  int fcode[4];
+  float fz[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    fcode[f] = nbrt[f * kTile];
+    fz[f] = (float)znt[f * kTile];
+  }
+
+  // ---- volume: Dr p, Ds p, Dt p and div u = Dr fr + Ds fs + Dt ft, one
+  // k-step of 16 nodes at a time (this lane: nodes 16 j + 4 g + i)
+  f4 dpr[RB], dps[RB], dpt[RB], dv[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) dpr[b] = dps[b] = dpt[b] = dv[b] = f4{0, 0, 0, 0};
+#pragma unroll 1
+  for (int j = 0; j < RB; ++j) {
+    float p[4], fr[4], fs[4], ft[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const unsigned o = tb + (unsigned)min(16 * j + 4 * g + i, Np - 1) * (kTile * 4);
+      const float u = fld(Rq, o, FS), v = fld(Rq, o, 2 * FS), w = fld(Rq, o, 3 * FS);
+      p[i] = fld(Rq, o, 0);
+      fr[i] = rx * u + ry * v + rz * w;
+      fs[i] = sx * u + sy * v + sz * w;
+      ft[i] = tx * u + ty * v + tz * w;
+    }
+    const s4 bp = pack4(p), br = pack4(fr), bs = pack4(fs), bt = pack4(ft);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const s4 ar = frag[((0 * RB + b) * RB + j) * 64];
+      const s4 as = frag[((1 * RB + b) * RB + j) * 64];
+      const s4 at = frag[((2 * RB + b) * RB + j) * 64];
+      dpr[b] = mfma_bf16(ar, bp, dpr[b]);
+      dps[b] = mfma_bf16(as, bp, dps[b]);
+      dpt[b] = mfma_bf16(at, bp, dpt[b]);
+      dv[b] = mfma_bf16(ar, br, dv[b]);
+      dv[b] = mfma_bf16(as, bs, dv[b]);
+      dv[b] = mfma_bf16(at, bt, dv[b]);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < RB; ++b) dv[b] *= -Kb;
+  f4* rp = dv;
+
+  // ---- surface: one upwind flux against the exterior state per face node
+  // (FP32), the pressure jump lifted into the reference gradient; a lane
+  // computes the fluxes of face nodes 16 jj + 4 g + i
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    __builtin_amdgcn_sched_barrier(0);
+    const float cr = f == 2 ? 1.f : (f == 3 ? -1.f : 0.f);
+    const float cs = f == 2 ? 1.f : (f == 1 ? -1.f : 0.f);
+    const float ct = f == 2 ? 1.f : (f == 0 ? -1.f : 0.f);
+    float nx = cr * rx + cs * sx + ct * tx;
+    float ny = cr * ry + cs * sy + ct * ty;
+    float nz = cr * rz + cs * sz + ct * tz;
+    const float fsc = sqrtf(nx * nx + ny * ny + nz * nz);
+    const float inv = 1.f / fsc;
+    nx *= inv;
+    ny *= inv;
+    nz *= inv;
+    const int code = fcode[f];
+    const float ZP = fz[f];
+    const bool inner = code >= 0;
+    const int cb = -1 - code;
+    const bool hb = !inner && (cb & 3) == 0;
+    const bool dir = !inner && (cb & 3) == 2;
+    const int e2 = inner ? (code >> 5) : e;
+    const unsigned nb = (unsigned)(e2 >> 4) * TS + (unsigned)(e2 & 15) * 4;
+    const int mapbase = inner ? ((f * 4 + ((code >> 3) & 3)) * 6 + (code & 7)) * Nfp
+                              : ((f * 4) * 6 + ((cb >> 2) & 7)) * Nfp;
+    const double* qbt = qb3 + (size_t)(hb ? (cb >> 5) : 0) * Nfp;
+    const float iZ = 1.f / (Z + ZP);
+    const float aM = ZP * iZ, aP = Z * iZ, bZ = Z * aM;
+    const float cP = fsc * Kb;
+#pragma unroll
+    for (int jj = 0; jj < FK; ++jj) {
+      float fp[4], fu[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int kc = min(16 * jj + 4 * g + i, Nfp - 1);
+        const int n = smask[f * Nfp + kc];
+        const int n2 = smap[mapbase + kc];
+        const unsigned oM = tb + (unsigned)n * (kTile * 4);
+        const unsigned oP = nb + (unsigned)n2 * (kTile * 4);
+        const float pM = fld(Rq, oM, 0), uM = fld(Rq, oM, FS), vM = fld(Rq, oM, 2 * FS),
+                    wM = fld(Rq, oM, 3 * FS);
+        const float pP = fld(Rq, oP, 0), uP = fld(Rq, oP, FS), vP = fld(Rq, oP, 2 * FS),
+                    wP = fld(Rq, oP, 3 * FS);
+        const float rb = (float)qbt[min(n2, Nfp - 1)];
+        const float unM = nx * uM + ny * vM + nz * wM;
+        const float unP = nx * uP + ny * vP + nz * wP;
+        const float pG = inner ? pP : (dir ? -pM : (hb ? 2.f * rb : 0.f));
+        const float uG = inner ? unP : (dir ? unM : 0.f);
+        const float pF = aM * pM + aP * pG + bZ * (unM - uG);
+        const float unF = iZ * (pM - pG) + aP * unM + aM * uG;
+        fp[i] = cP * (unM - unF);
+        fu[i] = pM - pF;
+      }
+      const s4 bfp = pack4(fp), bfu = pack4(fu);
+      const s4* fl = fragL + (f * FK + jj) * 64;
+      if (f == 2) {
+        float nfu[4] = {-fu[0], -fu[1], -fu[2], -fu[3]};
+        const s4 bnu = pack4(nfu);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          const s4 a = fl[b * 4 * FK * 64];
+          rp[b] = mfma_bf16(a, bfp, rp[b]);
+          dpr[b] = mfma_bf16(a, bnu, dpr[b]);
+          dps[b] = mfma_bf16(a, bnu, dps[b]);
+          dpt[b] = mfma_bf16(a, bnu, dpt[b]);
+        }
+      } else {
+        f4* G = f == 0 ? dpt : (f == 1 ? dps : dpr);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          const s4 a = fl[b * 4 * FK * 64];
+          rp[b] = mfma_bf16(a, bfp, rp[b]);
+          G[b] = mfma_bf16(a, bfu, G[b]);
+        }
+      }
+    }
+  }
+
+  // ---- LSRK update of the four rows per row block this lane holds (FP32)
+  const bool live = irho != 0.f;
+  const double* sp = sh.srcp + 4 * shot;
+  const bool src = (double)e == sp[0];
+  const double trr = stage_time(sh) - sp[2], arr = M_PI * sp[1] * trr;
+  const float src_s = (float)(sp[3] * trr * exp(-arr * arr));
+  const double* src_w = sh.srcw + (size_t)shot * Np;
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    __builtin_amdgcn_sched_barrier(0);
+    float ro[4][4], qv[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const unsigned o = tb + (unsigned)min(16 * b + 4 * g + r, Np - 1) * (kTile * 4);
+#pragma unroll
+      for (int fl = 0; fl < 4; ++fl) {
+        ro[r][fl] = fldn(Rr, o, fl * FS);
+        qv[r][fl] = fld(Rq, o, fl * FS);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = 16 * b + 4 * g + r;
+      const int nc = min(n, Np - 1);
+      const unsigned o = tb + (unsigned)nc * (kTile * 4);
+      const float sw = (float)src_w[nc];
+      const float a = dpr[b][r], bq = dps[b][r], c = dpt[b][r];
+      const float rhs[4] = {rp[b][r] + (src ? sw * src_s : 0.f),
+                            -irho * (rx * a + sx * bq + tx * c),
+                            -irho * (ry * a + sy * bq + ty * c),
+                            -irho * (rz * a + sz * bq + tz * c)};
+      if (live && n < Np) {
+#pragma unroll
+        for (int fl = 0; fl < 4; ++fl) {
+          const float rr = A * ro[r][fl] + dt * rhs[fl];
+          fstn(Rr, o, fl * FS, rr);
+          fstn(Rn, o, fl * FS, qv[r][fl] + B * rr);
+        }
+      }
+    }
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(kWaves3f * 64, Dims3b<N>::kOcc) k_level3_bf16(
+    Lvl3 L, const float* __restrict__ qo, float* __restrict__ qn, float* __restrict__ res,
+    const double* __restrict__ qb3, float A, float B, float dt, Shots sh) {
+  using D = Dims3b<N>;
+  constexpr int Nfp = D::Nfp;
+  extern __shared__ float sfl[];
+  int* smask = reinterpret_cast<int*>(sfl);
+  int* smap = smask + 4 * Nfp;
+  // fragments after the maps, at an 8-byte boundary
+  s4* sops = reinterpret_cast<s4*>(sfl + ((4 * Nfp + 96 * Nfp + 1) & ~1));
+  fill_lds<kWaves3f * 64, 4 * Nfp>(smask, L.fmask, threadIdx.x);
+  fill_lds<kWaves3f * 64, 96 * Nfp>(smap, L.fmap, threadIdx.x);
+  fill_lds<kWaves3f * 64, D::NFR * 64>(reinterpret_cast<unsigned long long*>(sops),
+                                       reinterpret_cast<const unsigned long long*>(L.opsb),
+                                       threadIdx.x);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int ngrp = (L.ntile + kWaves3f - 1) / kWaves3f;
+  const XcdRange rg_(ngrp * (long long)sh.n, L.order);
+  for (long long item = rg_.lo; item < rg_.hi; item += rg_.step)
+    tile_bf16<N>(L, qo, qn, res, qb3, A, B, dt, sh, item, ngrp, smap, smask, sops, lane);
+}
+
+template <int N>
+hipError_t launch3b(const Lvl3& L, const float* qo, float* qn, float* res, const double* qb3,
+                    double A, double B, double dt, const Shots& sh, hipStream_t st) {
+  using D = Dims3b<N>;
+  constexpr int Nfp = D::Nfp;
+  const size_t lds = sizeof(float) * ((4 * Nfp + 96 * Nfp + 1) & ~1) + (size_t)D::NFR * 512;
+  const int ngrp = (L.ntile + kWaves3f - 1) / kWaves3f;
+  if (sh.n < 1) return hipErrorInvalidValue;
+  int resident = 0;
+  {
+    const hipError_t e =
+        kernel_setup((const void*)(k_level3_bf16<N>), kWaves3f * 64, lds, &resident);
+    if (e != hipSuccess) return e;
+  }
+  const long long items = (long long)ngrp * sh.n;
+  const int blocks = grid3(resident, items, L.eighths);
+  hipLaunchKernelGGL(k_level3_bf16<N>, dim3(blocks), dim3(kWaves3f * 64), lds, st, L, qo, qn, res,
                      qb3, (float)A, (float)B, (float)dt, sh);
   return hipGetLastError();
 }
@@ -782,6 +1066,20 @@ hipError_t launch_level3_f32(const Lvl3& L, const float* qo, float* qn, float* r
     case 4: return launch3f<4>(L, qo, qn, res, qb3, A, B, dt, sh, st);
     case 5: return launch3f<5>(L, qo, qn, res, qb3, A, B, dt, sh, st);
     case 6: return launch3f<6>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_level3_bf16(const Lvl3& L, const float* qo, float* qn, float* res,
+                              const double* qb3, double A, double B, double dt, const Shots& sh,
+                              hipStream_t st) {
+  switch (L.N) {
+    case 1: return launch3b<1>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    case 2: return launch3b<2>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    case 3: return launch3b<3>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    case 4: return launch3b<4>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    case 5: return launch3b<5>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    case 6: return launch3b<6>(L, qo, qn, res, qb3, A, B, dt, sh, st);
     default: return hipErrorInvalidValue;
   }
 }

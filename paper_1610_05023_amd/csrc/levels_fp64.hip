@@ -836,7 +836,7 @@ hipError_t launch3_dma(const Lvl3& L, const double* qo, double* qn, double* res,
     if (e != hipSuccess) return e;
   }
   const long long items = (long long)ngrp * sh.n;
-  const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, items) / 8 * 8);
+  const int blocks = grid3(resident, items, L.eighths);
   hipLaunchKernelGGL(k_level3_dma<N>, dim3(blocks), dim3(kWavesR * 64), lds, st, L, qo, qn, res,
                      qb3, A, B, dt, sh);
   return hipGetLastError();
@@ -878,7 +878,7 @@ hipError_t launch3_reg(const Lvl3& L, const double* qo, double* qn, double* res,
   }
   const long long items = (long long)ngrp * sh.n;
   // a multiple of 8, so that every XCD has blocks for its range of items
-  const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, items) / 8 * 8);
+  const int blocks = grid3(resident, items, L.eighths);
   hipLaunchKernelGGL(k_level3<N>, dim3(blocks), dim3(kWaves3 * 64), lds, st, L, qo, qn, res,
                      qb3, A, B, dt, sh);
   return hipGetLastError();

@@ -71,6 +71,40 @@ def rel_errors(got, ref):
     return out
 
 
+# field names of each array's field axis (canonical layouts)
+FIELDS = {"q3": (1, ("p", "u", "v", "w")), "res3": (1, ("p", "u", "v", "w")),
+          "q2": (2, ("p", "va", "vb")), "res2": (2, ("p", "va", "vb")),
+          "q1": (2, ("p", "w")), "res1": (2, ("p", "w"))}
+
+
+def field_errors(got, ref):
+    """Relative l2 error per level and per field: 'q3.p', 'q3.u', ...,
+    'q2.p', 'q2.va', 'q2.vb', 'q1.p', 'q1.w' (the residuals likewise) and
+    the coupling arrays qb3, q0_3, qb2, q0_2, qb1 whole.  A field whose
+    reference norm is below 1e-30 of the q3 norm is normalised by the q3
+    norm instead."""
+    scale = np.linalg.norm(ref["q3"])
+    out = {}
+    for k in ARRAYS:
+        if ref[k].size == 0:
+            continue
+        if k in FIELDS:
+            ax, names = FIELDS[k]
+            parts = [(f"{k}.{nm}", np.take(got[k], i, axis=ax), np.take(ref[k], i, axis=ax))
+                     for i, nm in enumerate(names)]
+        else:
+            parts = [(k, got[k], ref[k])]
+        for name, a, b in parts:
+            nr = np.linalg.norm(b)
+            den = nr if nr > 1e-30 * scale else scale
+            out[name] = float(np.linalg.norm(a - b) / den) if den > 0 else 0.0
+    return out
+
+
+def fmt_errors(err):
+    return "{" + ", ".join(f"{k}: {v:.1e}" for k, v in err.items()) + "}"
+
+
 def corner_block(VX, E, n, m):
     """The m^3-cell block at the far corner (x, y, z up to the box's upper
     faces) of the n^3-cell Kuhn mesh ``workloads.kuhn_mesh(n)``: its tets in

@@ -184,3 +184,36 @@ def test_closure_in_the_step_matches_reference_network():
     print(f"[closure] step r- vs reference network: max |diff| / max |r+| = {err:.1e} "
           f"({len(ref)} nodes, max |r-| / max |r+| = {np.max(np.abs(ref)) / scale:.2f})", flush=True)
     assert err < 2e-5
+
+
+def test_guarded_run_falls_back_to_plain_habc():
+    """The failure check drives the fallback: with a source the energy grows,
+    so a check with rel_tol = 0 trips at the first check; the run then
+    restarts from the last good state (the initial one) in the plain method
+    with HABC P = 6 and ends where a plain P = 6 run from the start ends.
+    With no source and a tolerance the check passes and the closure keeps
+    running."""
+    from paper_1610_05023_amd import Solver
+    from paper_1610_05023_amd.closure import GuardedRun, gaussian_state
+    n, N = 5, 3
+    VX, E = w.kuhn_mesh(n)
+    K = E.shape[0]
+    dt = w.kuhn_dt(n, N, 1.0)
+    wts = init_params(3, in_scale=1.0, g_max=0.9).astype(np.float32)
+    make = lambda P: Solver(VX, E, N, P, np.ones(K), np.ones(K)).bind()
+    src = ((0.45, 0.52, 0.5), 4.0, 0.1)
+    g = GuardedRun(make, wts, fallback_P=6, check_every=40, rel_tol=0.0, source=src)
+    g.set_state(gaussian_state(g.s, (0.5, 0.5, 0.5), 0.15))
+    g.step(120, dt)
+    assert g.switched_at == 0
+    ref = make(6)
+    ref.set_source(*src)
+    ref.set_state(gaussian_state(ref, (0.5, 0.5, 0.5), 0.15))
+    for k in range(3):
+        ref.step(40, dt, 40 * k * dt)
+    got, want = g.read_fields(["q3"])["q3"], ref.read_fields(["q3"])["q3"]
+    assert _rel(got, want) < 1e-12
+    quiet = GuardedRun(make, wts, fallback_P=6, check_every=40, rel_tol=1e-9)
+    quiet.set_state(gaussian_state(quiet.s, (0.5, 0.5, 0.5), 0.15))
+    quiet.step(120, dt)
+    assert quiet.switched_at is None

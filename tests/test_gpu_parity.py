@@ -6,14 +6,18 @@ import numpy as np
 import pytest
 
 import workloads as w
-from parity_util import (ARRAYS, block_maps, block_sample, corner_block, make_case,
-                         make_solver, rel_errors, run_oracle)
+from parity_util import (ARRAYS, block_maps, block_sample, corner_block, field_errors,
+                         fmt_errors, make_case, make_solver, rel_errors, run_oracle)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 
-def _check(case, steps, dt, t0=0.0, tol=TOL, precision=0):
+def _check(case, steps, dt, t0=0.0, tol=TOL, precision=0, tol_res=None):
+    """Steps the library and the oracle; every array's relative l2 error
+    must be <= tol (the residual arrays <= tol_res when given: they are
+    differences of nearly equal stage values, so a rounding variant's
+    relative error there is far larger)."""
     print(f"[parity] N={case['N']} P={case['P']} K={case['E'].shape[0]} steps={steps} "
           f"precision={precision}", flush=True)
     s = make_solver(case, precision=precision)
@@ -22,7 +26,8 @@ def _check(case, steps, dt, t0=0.0, tol=TOL, precision=0):
     ref = run_oracle(case, steps, dt, t0)
     err = rel_errors(got, ref)
     print("[parity] errors", {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
-    bad = {k: v for k, v in err.items() if not v <= tol}
+    lim = {k: (tol_res if tol_res is not None and k.startswith("res") else tol) for k in err}
+    bad = {k: v for k, v in err.items() if not v <= lim[k]}
     assert not bad, bad
     return s, got, ref
 
@@ -74,42 +79,67 @@ def test_wave_through_faces_edges_corners():
     assert np.abs(ref["qb1"]).max() > 1e-8
 
 
-@pytest.mark.parametrize("name,precision", [("1b", 0), ("3", 0), ("3", 2)])
-def test_thousand_steps_against_stored_oracle(name, precision):
-    """1000 steps of the 8^3 x 6 Gaussian case with HABC P = 3 on all faces,
-    at N = 3 (config 1b) and N = 5 (the precision case), against the
-    oracle's run stored in tests/golden/long_runs.json. That file is written
-    by make_long_runs.py from the oracle alone and holds, per array, the l2
-    norm and 128 evenly spaced values. By step 1000 the pulse has crossed the
-    faces, edges and corners and mostly left the domain, so differences are
-    measured on the scale of the initial field, which sets the round-off:
-    pointwise against the initial peak, norms against the initial q3 norm.
-    The bounds are 1e-11 in FP64 and 1e-4 for the FP32 variant."""
-    import json
+_LONG = {}
+
+
+def _long_runs():
     import os
-    with open(os.path.join(os.path.dirname(__file__), "golden", "long_runs.json")) as f:
-        g = json.load(f)[name]
+    if not _LONG:
+        path = os.path.join(os.path.dirname(__file__), "golden", "long_runs.npz")
+        with np.load(path) as z:
+            _LONG.update({k: z[k] for k in z.files})
+    return _LONG
+
+
+# errors against the stored oracle: FP64 at round-off; the mixed forms get
+# regression guards a few times above their measured errors
+LONG_TOL = {0: {100: 1e-12, 1000: 1e-10}, 2: {100: 1e-3, 1000: 1e-3},
+            3: {100: 5e-2, 1000: 1e-1}}
+
+
+@pytest.mark.parametrize("name,precision", [("1b", 0), ("3", 0), ("3", 2), ("3", 3)])
+def test_thousand_steps_against_stored_oracle(name, precision):
+    """The 8^3 x 6 Gaussian case with HABC P = 3 on all faces, at N = 3
+    (config 1b) and N = 5 (the precision case), against the oracle's full
+    state after 1000 steps stored in tests/golden/long_runs.npz (written by
+    make_long_runs.py from the oracle alone), and at 100 steps against the
+    FP64 library (itself held to the oracle at 1e-12).  Relative l2 error
+    per level and per field (p, u, v, w of q3; p_i and the two tangential
+    velocities of q2; p_ij and w of q1; residuals alike; the coupling arrays
+    whole).  FP64 is held to round-off; the FP32 and BF16 contraction
+    variants report their errors against FP64 with a regression guard."""
+    g = _long_runs()
     cfg = w.config(name)
-    assert (g["n"], g["N"], g["P"], g["steps"]) == (cfg.n, cfg.N, cfg.P, cfg.steps)
+    n, N, P, dt = g[f"{name}/meta"]
+    assert (int(n), int(N), int(P), dt) == (cfg.n, cfg.N, cfg.P, cfg.dt)
     case = make_case(n=cfg.n, N=cfg.N, P=cfg.P, width=cfg.extra["width"])
-    q0 = g["q3_initial_norm"]
+    q0 = float(g[f"{name}/q3_initial_norm"])
     assert abs(float(np.linalg.norm(case["state"]["q3"])) - q0) <= 1e-14 * q0
-    peak = float(np.abs(case["state"]["q3"]).max())
     s = make_solver(case, precision=precision)
-    s.step(cfg.steps, cfg.dt)
-    got = s.read_fields()
     worst = {}
-    for k, rec in g["arrays"].items():
-        a = got[k].reshape(-1)
-        assert a.size == rec["size"], k
-        d_pt = float(np.abs(a[np.array(rec["index"])] - np.array(rec["values"])).max())
-        d_nm = abs(float(np.linalg.norm(a)) - rec["norm"])
-        worst[k] = max(d_pt / peak, d_nm / q0)
-    print(f"[long] config {name} precision {precision}: q3 norm {g['arrays']['q3']['norm']:.3e} "
-          f"(initial {q0:.3e}); differences", {k: f"{v:.1e}" for k, v in worst.items()},
-          flush=True)
-    tol = 1e-11 if precision == 0 else 1e-4
-    assert all(v <= tol for v in worst.values()), worst
+    for snap in (100, 1000):
+        done = 100 if snap == 1000 else 0
+        s.step(snap - done, cfg.dt, done * cfg.dt)
+        got = s.read_fields()
+        if snap == 1000:
+            ref = {k: g[f"{name}/{snap}/{k}"] for k in ARRAYS}
+            against = "stored oracle"
+        else:
+            if precision == 0:
+                continue
+            s64 = make_solver(case)
+            s64.step(snap, cfg.dt)
+            ref = s64.read_fields()
+            against = "FP64 library"
+        err = field_errors(got, ref)
+        print(f"[long] config {name} precision {precision} step {snap} vs {against}: "
+              f"{fmt_errors(err)}", flush=True)
+        # BF16: the 3D fields are guarded, the rest reported (as in
+        # test_mixed_precision_error)
+        keep = err if precision != 3 else {k: v for k, v in err.items() if k.startswith("q3.")}
+        worst[snap] = max(keep.values())
+    tol = LONG_TOL[precision]
+    assert all(worst[k] <= tol[k] for k in worst), (worst, tol)
 
 
 def test_layered_medium_with_source():
@@ -135,7 +165,8 @@ def test_mixed_faces_random():
 
 
 @pytest.mark.parametrize("n,N,precision", [(3, 3, 0), (4, 3, 0), (4, 3, 2), (3, 5, 0), (3, 5, 2),
-                                           (3, 1, 0), (3, 6, 0), (3, 2, 2), (3, 6, 2)])
+                                           (3, 1, 0), (3, 6, 0), (3, 2, 2), (3, 6, 2),
+                                           (4, 3, 3), (3, 5, 3), (3, 1, 3), (3, 6, 3)])
 def test_general_mesh_random_medium(n, N, precision):
     """An unstructured mesh (n^3 Kuhn cells with the interior vertices moved
     by up to 0.1 h, the elements shuffled, each element's vertices rotated;
@@ -146,7 +177,10 @@ def test_general_mesh_random_medium(n, N, precision):
     162 elements, so the last tile of the layout is ragged.  N <= 4 runs the
     tile-on-chip 3D kernels, N = 5, 6 the register-streaming ones.  The FP32
     variant (precision 2) is held to 1e-4, the guard of its rounding error
-    on the Kuhn mesh."""
+    on the Kuhn mesh; the BF16 contractions (precision 3) to 1e-2 in the
+    state and 0.3 in the residuals, guards a few times above their measured
+    rounding errors (2e-3 and 0.1: about 8 bits of mantissa per contraction
+    input over 30 steps)."""
     from oracle.solver import Oracle
     P = 3
     VX, E = w.general_mesh(n, amp=0.1, seed=5)
@@ -160,8 +194,9 @@ def test_general_mesh_random_medium(n, N, precision):
     case = dict(VX=VX, E=E, N=N, P=P, rho=rho, c=c, face_bc=fb, periodic=per, oracle=o,
                 state=state, source=((0.43, 0.55, 0.47), 4.0, 0.1),
                 box=np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0]))
-    _check(case, 30, 0.5 * w.kuhn_dt(n, N, 3.0), tol=TOL if precision == 0 else 1e-4,
-           precision=precision)
+    _check(case, 30, 0.5 * w.kuhn_dt(n, N, 3.0),
+           tol={0: TOL, 2: 1e-4, 3: 1e-2}[precision], precision=precision,
+           tol_res=0.3 if precision == 3 else None)
 
 
 def test_largest_mesh_far_corner_against_oracle():
@@ -337,38 +372,52 @@ def test_full_size_layered_one_step():
     _check(case, 1, w.kuhn_dt(n, 4, 3.0), t0=0.01)
 
 
-@pytest.mark.parametrize("N", [4, 5])
-def test_fp32_variant_error(N):
-    """FP32 3D level (FP32 state, FP32 MFMA), FP64 boundary levels: its error
-    against the FP64 oracle (10 steps) and the FP64 library (200 steps),
-    per array, on the 8^3 x 6 mesh with HABC P = 3 on all faces and a
-    centred Gaussian that reaches the faces.  Rounding only: the bound is a
-    regression guard at a few hundred FP32 ulps, not a parity claim."""
+# FP32: every field, at 10, 200 and 1000 steps; BF16: the 3D fields (the
+# other levels and the residuals hold values far below the pulse's size
+# early on, where relative errors say little: reported, not guarded)
+MIXED_TOL = {2: (3e-4, 1e-3, 5e-2), 3: (5e-2, 5e-2, 1e-1)}
+
+
+@pytest.mark.parametrize("N,precision", [(4, 2), (5, 2), (4, 3), (5, 3)])
+def test_mixed_precision_error(N, precision):
+    """FP32 3D state with the volume and LIFT contractions on the FP32 MFMA
+    (precision 2) or the BF16 MFMA (precision 3), FP64 boundary levels: the
+    error per level and field against the FP64 oracle (10 steps) and the
+    FP64 library (200 and 1000 steps), on the 8^3 x 6 mesh with HABC P = 3
+    on all faces and a centred Gaussian that reaches the faces.  Rounding
+    only: the bounds are regression guards, not parity claims."""
     n = 8
     case = make_case(n=n, N=N, P=3, init="gaussian", width=0.15)
     dt = w.kuhn_dt(n, N, 1.0)
-    s32 = make_solver(case, precision=2)
-    s32.step(10, dt)
-    e10 = rel_errors(s32.read_fields(), run_oracle(case, 10, dt))
-    print(f"[fp32] N={N} 10 steps vs oracle", {k: f"{v:.1e}" for k, v in e10.items()}, flush=True)
-    s32.step(190, dt, 10 * dt)
+    tag = {2: "fp32", 3: "bf16"}[precision]
+    sx = make_solver(case, precision=precision)
+    sx.step(10, dt)
+    e10 = field_errors(sx.read_fields(), run_oracle(case, 10, dt))
+    print(f"[{tag}] N={N} 10 steps vs oracle {fmt_errors(e10)}", flush=True)
+    sx.step(190, dt, 10 * dt)
     s64 = make_solver(case)
     s64.step(200, dt)
-    e200 = rel_errors(s32.read_fields(), s64.read_fields())
-    print(f"[fp32] N={N} 200 steps vs FP64", {k: f"{v:.1e}" for k, v in e200.items()}, flush=True)
-    assert max(e10.values()) < 1e-4 and max(e200.values()) < 1e-3, (e10, e200)
+    e200 = field_errors(sx.read_fields(), s64.read_fields())
+    print(f"[{tag}] N={N} 200 steps vs FP64 {fmt_errors(e200)}", flush=True)
     # 1000 steps (the FP64 library stands in for the oracle: it matches it to
     # round-off); the pulse has mostly left through the HABC by then
-    s32.step(800, dt, 200 * dt)
+    sx.step(800, dt, 200 * dt)
     s64.step(800, dt, 200 * dt)
-    e1000 = rel_errors(s32.read_fields(), s64.read_fields())
-    print(f"[fp32] N={N} 1000 steps vs FP64", {k: f"{v:.1e}" for k, v in e1000.items()},
-          f"energy {s32.energy():.3e} vs {s64.energy():.3e}", flush=True)
-    assert max(e1000.values()) < 5e-2, e1000
-    assert s32.check()[0] == "DGH_OK"
+    e1000 = field_errors(sx.read_fields(), s64.read_fields())
+    print(f"[{tag}] N={N} 1000 steps vs FP64 {fmt_errors(e1000)}; energy {sx.energy():.4e} "
+          f"vs {s64.energy():.4e}", flush=True)
+    t10, t200, t1000 = MIXED_TOL[precision]
+    pick = (lambda e: e) if precision == 2 else (
+        lambda e: {k: v for k, v in e.items() if k.startswith("q3.")})
+    assert max(pick(e10).values()) < t10 and max(pick(e200).values()) < t200, (e10, e200)
+    assert max(pick(e1000).values()) < t1000, e1000
+    # the energy left after 1000 steps (the pulse has mostly gone): FP32 to
+    # rounding, BF16 within 10%
+    assert abs(sx.energy() / s64.energy() - 1) < (1e-5 if precision == 2 else 1e-1)
+    assert sx.check()[0] == "DGH_OK"
 
 
-@pytest.mark.parametrize("precision", [0, 2])
+@pytest.mark.parametrize("precision", [0, 2, 3])
 def test_graph_replay_equals_eager(precision):
     """Replayed stepping (one captured HIP graph per step, stage times from
     the device clock) gives the same bits as eager stepping: two shots with
@@ -403,20 +452,21 @@ def test_graph_replay_equals_eager(precision):
     print(f"[graph] precision {precision}: replayed == eager bitwise", flush=True)
 
 
-@pytest.mark.parametrize("precision", [0, 2])
-def test_tuning_candidates_and_autotune(precision):
+@pytest.mark.parametrize("precision,N", [(0, 4), (2, 4), (3, 4), (2, 5)])
+def test_tuning_candidates_and_autotune(precision, N):
     """Every launch candidate of the 3D level (tile on chip / register
     streaming x XCD ranges / round robin) matches the oracle on a layered
     medium with a source (FP64 to round-off, the FP32 variant to its error
     level); autotune leaves the state as it was and picks one of them."""
-    n, N, P, steps, dt = 5, 4, 3, 6, 1e-3
-    tol = TOL if precision == 0 else 1e-3
+    n, P, steps, dt = 5, 3, 6, 1e-3
+    tol = {0: TOL, 2: 1e-3, 3: 1e-2}[precision]
+    tol_res = 0.3 if precision == 3 else tol          # residuals: see _check
     case = make_case(n=n, N=N, P=P, medium="layered", init="random", seed=57,
                      source=((0.41, 0.52, 0.33), 6.0, 0.02))
     ref = run_oracle(case, steps, dt)
     s = make_solver(case, precision=precision)
     count = s.tuning_count()
-    assert count == 4
+    assert count == (6 if precision == 3 else 12)
     for cand in range(count):
         s.set_state(case["state"])
         s.set_tuning(cand)
@@ -424,7 +474,8 @@ def test_tuning_candidates_and_autotune(precision):
         err = rel_errors(s.read_fields(), ref)
         print(f"[tuning] precision {precision} candidate {cand}: max error "
               f"{max(err.values()):.1e}", flush=True)
-        assert max(err.values()) <= tol, (cand, err)
+        assert all(v <= (tol_res if k.startswith("res") else tol) for k, v in err.items()), \
+            (cand, err)
     s.set_state(case["state"])
     before = s.read_fields()
     best, ms = s.autotune(5)
@@ -435,7 +486,7 @@ def test_tuning_candidates_and_autotune(precision):
     s.step(steps, dt)
     err = rel_errors(s.read_fields(), ref)
     print(f"[tuning] autotune picked {best}, ms/launch {np.round(ms, 4)}", flush=True)
-    assert max(err.values()) <= tol, err
+    assert all(v <= (tol_res if k.startswith("res") else tol) for k, v in err.items()), err
 
 
 def test_checkpoint_resume_is_bitwise():
@@ -544,3 +595,6 @@ def test_group_step_equals_separate_runs(precision):
     s4 = make_solver(same_n, precision=2 - precision)
     with pytest.raises(DghError):
         step_group([group[0], s4], 1, dt)
+    s5 = make_solver(same_n, precision=3)        # the BF16 variant has no group kernel
+    with pytest.raises(DghError):
+        step_group([s5], 1, dt)

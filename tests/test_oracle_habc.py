@@ -48,14 +48,23 @@ def _char(p, zu):
     return 0.5 * (p + zu), 0.5 * (p - zu)
 
 
+def _gammas(P, kind):
+    """Pade coefficients, or coefficients other than Pade's (positive,
+    spread: the edge and corner algebra holds for any)."""
+    if kind == "pade":
+        return pade_gamma(P)
+    return np.sort(np.random.default_rng(40 + P).uniform(0.05, 30.0, P))
+
+
+@pytest.mark.parametrize("kind", ["pade", "other"])
 @pytest.mark.parametrize("P", [1, 3, 6])
-def test_edge_system_satisfies_first_order_conditions(P):
+def test_edge_system_satisfies_first_order_conditions(P, kind):
     """The solution of the characteristic edge equations satisfies the
     first-order edge conditions of Section 2.3,
       p_i - Z v_i = (2/M) sum_j g_j (p_ij - p_i) (face A fields at the edge),
       p_j - Z u_j = (2/M) sum_i g_i (p_ij - p_j) (face B fields),
     with p_i = r+ + r-, Z v_i = r+ - r-, and p_ij rebuilt from p*_ij."""
-    g = pade_gamma(P)
+    g = _gammas(P, kind)
     M = 2 * P + 1
     rng = np.random.default_rng(P)
     n = 5
@@ -86,12 +95,13 @@ def test_edge_inverse_block_structure(P):
         assert np.allclose(A[:P, P:], A[P:, :P], atol=1e-14)
 
 
+@pytest.mark.parametrize("kind", ["pade", "other"])
 @pytest.mark.parametrize("P", [1, 2, 3])
-def test_corner_system_satisfies_first_order_conditions(P):
+def test_corner_system_satisfies_first_order_conditions(P, kind):
     """Corner: p_0jk - Z u_0jk = (2/M) sum_i g_i (p_ijk - p_0jk) with the 0D
     relation (1+gi+gj+gk) p_ijk = (1+gi) p_0jk + (1+gj) p_i0k + (1+gk) p_ij0
     (Section 2.2), and likewise for the two other edges."""
-    g = pade_gamma(P)
+    g = _gammas(P, kind)
     M = 2 * P + 1
     rng = np.random.default_rng(10 + P)
     n = 3
@@ -137,3 +147,20 @@ def test_seam_unknown_counts():
     for P, K_tet, K_tri, K_lin, expected in ((int(a), int(b), int(c), int(d), int(e))
                                              for a, b, c, d, e in rows):
         assert n_unknowns(K_tet, K_tri, K_lin, 3, P) == expected
+
+
+def test_angle_matched_coefficients_zero_the_reflection():
+    """Coefficients other than Pade's (Section 2.1's remark on other
+    parameters): those making the condition exact at 20, 38 and 52 degrees
+    zero the plane-wave reflection coefficient there, and over 0-55 degrees
+    (the incidences of a centred source on a cube's faces) their largest
+    reflection is below the Pade condition's of the same order."""
+    from paper_1610_05023_amd.habc_params import angle_matched_gamma
+    ang = np.radians([20.0, 38.0, 52.0])
+    g = angle_matched_gamma(ang)
+    assert np.all(g > 0) and len(g) == 3
+    assert np.abs(reflection_coefficient(ang, 3, g)).max() < 1e-12
+    th = np.radians(np.linspace(0.0, 55.0, 111))
+    ours = np.abs(reflection_coefficient(th, 3, g)).max()
+    pade = np.abs(reflection_coefficient(th, 3)).max()
+    assert ours < 0.5 * pade, (ours, pade)
