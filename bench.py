@@ -406,6 +406,8 @@ def main():
     ap.add_argument("--teacher", choices=["small", "case"], default="small",
                     help="reflection --closure: teacher runs of the small recipe (8^3, c = 1) "
                          "or on the case's own mesh and medium")
+    ap.add_argument("--candidate", type=int, default=None,
+                    help="force a launch tuning candidate of the 3D level")
     ap.add_argument("--tuning-cache", default=None,
                     help="--autotune: JSON file of stored choices (default: "
                          "$DGHABC_TUNING_CACHE or ~/.cache/dghabc/tuning.json)")
@@ -486,6 +488,9 @@ def main():
         wts[0], wts[1] = 1.0, 0.95
         s.set_closure(wts)
     tuned = None
+    if args.candidate is not None:
+        s.set_tuning(args.candidate)
+        tuned = {"candidate": args.candidate, "forced": True}
     if args.autotune:
         from paper_1610_05023_amd.tuning import tune
         best, ms, cached = tune(s, args.tuning_cache, 10)
