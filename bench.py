@@ -518,6 +518,19 @@ def main():
         torch.cuda.synchronize()
     ms3, n3 = s.kernel_time(3)
     s.kernel_timing(False)
+    # measured device copy (torch, 2 x 1 GiB moved per copy) as a second
+    # bandwidth reference beside the nominal peak
+    xa = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    xb = torch.empty_like(xa)
+    for _ in range(3):
+        xb.copy_(xa)
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    for _ in range(10):
+        xb.copy_(xa)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * xa.numel() * 8 / ((time.perf_counter() - tc) / 10) / 1e9
+    del xa, xb
     finite = all(s.check(shot=j)[0] == "DGH_OK" for j in range(nsh))
     value = U * 5 * args.steps / el
     avg3_ms = ms3 / max(n3, 1)
@@ -581,6 +594,8 @@ def main():
                                 " (3D volume + surface + LSRK update)"),
                      "avg_us": avg3_ms * 1e3, "alg_bytes_per_launch": alg,
                      "step_achieved": step_gbs, "step_frac": step_gbs / HBM_PEAK_GBS,
+                     "measured_copy_gbs": copy_gbs,
+                     "frac_of_measured_copy": achieved / copy_gbs,
                      "step_alg_bytes": step_alg,
                      "step_note": "all levels' algorithmic bytes per step / ms_per_step"},
         "cpu_baseline": cpu,

@@ -277,6 +277,14 @@ dgh_status dgh_mlp_grad(const float* W, const float* X, const float* T, int n, f
 dgh_status dgh_mlp_adam(float* W, const float* G, float* M, float* V, int t, float lr,
                         void* stream);
 
+/* dgh_mlp_grad in BF16 on the matrix cores: the weights (FP32, the master
+ * copy) and the activations and their gradients are rounded to BF16 as they
+ * enter each product, every sum is FP32; the same arguments, work buffer
+ * and loss.  Results differ from dgh_mlp_grad by that rounding (about 1%
+ * of the gradient). */
+dgh_status dgh_mlp_grad_bf16(const float* W, const float* X, const float* T, int n, float* G,
+                             float* work, double* loss, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving or training loops, harnesses that forbid
  * hipMalloc): dgh_mlp_grad without the work argument.  Same kernels and

@@ -7,9 +7,11 @@ W3[64][64], b3[64], W4[64], b4.  Network: x -> tanh(W1 s x + b1) ->
 tanh(W2 . + b2) -> tanh(W3 . + b3) -> y = W4 . + b4, with s the input
 scale and x the 10 raw inputs divided by their root mean square (plus
 1e-30 under the root); the closure's r- is g_max tanh(y) r+.  A sample row
-is X[11]: the raw inputs (p and Z |u_t| now and at 4 earlier step ends),
-then r+, the outgoing characteristic (p + Z n.u) / 2.  The gradient is checked against central finite differences in
-the tests, so the backward formulas below are pinned independently.
+is X[11]: the 10 raw inputs (p and Z |u_t| now, then the square roots of
+their running mean squares over 4 time scales), then r+, the outgoing
+characteristic (p + Z n.u) / 2.  The network does not depend on what the
+inputs mean.  The gradient is checked against central finite differences
+in the tests, so the backward formulas below are pinned independently.
 """
 from __future__ import annotations
 

@@ -57,6 +57,8 @@ _SIGS = {
                      C.POINTER(C.c_double), C.c_void_p],
     "dgh_mlp_adam": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_float,
                      C.c_void_p],
+    "dgh_mlp_grad_bf16": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                          C.POINTER(C.c_double), C.c_void_p],
     "dgh_mlp_grad_static": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
                             C.POINTER(C.c_double), C.c_void_p],
     "dgh_kernel_timing": [C.c_void_p, C.c_int],
@@ -337,14 +339,15 @@ def mlp_forward(W, X):
     return Y
 
 
-def mlp_grad(W, X, T, G, work, with_loss=True):
-    """Gradient of the mean squared error into G; returns the loss (or None)."""
+def mlp_grad(W, X, T, G, work, with_loss=True, bf16=False):
+    """Gradient of the mean squared error into G (FP32, or BF16 products on
+    the matrix cores); returns the loss (or None)."""
     loss = C.c_double()
-    _check(load().dgh_mlp_grad(C.c_void_p(W.data_ptr()), C.c_void_p(X.data_ptr()),
-                               C.c_void_p(T.data_ptr()), int(X.shape[0]),
-                               C.c_void_p(G.data_ptr()), C.c_void_p(work.data_ptr()),
-                               C.byref(loss) if with_loss else None, _stream(X)),
-           "dgh_mlp_grad")
+    fn = load().dgh_mlp_grad_bf16 if bf16 else load().dgh_mlp_grad
+    _check(fn(C.c_void_p(W.data_ptr()), C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()),
+              int(X.shape[0]), C.c_void_p(G.data_ptr()), C.c_void_p(work.data_ptr()),
+              C.byref(loss) if with_loss else None, _stream(X)),
+           "dgh_mlp_grad_bf16" if bf16 else "dgh_mlp_grad")
     return loss.value if with_loss else None
 
 

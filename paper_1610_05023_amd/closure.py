@@ -59,9 +59,11 @@ def init_params(rng, in_scale, g_max):
     return w
 
 
-def train(X, Y, iters=3000, batch=4096, lr=1e-3, seed=5, log_every=0, g_max=0.95):
+def train(X, Y, iters=3000, batch=4096, lr=1e-3, seed=5, log_every=0, g_max=0.95, bf16=False):
     """Adam on the mean squared error of r-; returns (parameters, losses).
-    The network's reflection gain is bounded by g_max (|g_max| <= 1)."""
+    The network's reflection gain is bounded by g_max (|g_max| <= 1).
+    bf16: the gradient's products in BF16 on the matrix cores (FP32 master
+    weights and Adam)."""
     import torch
     dev = torch.device("cuda", 0)
     rng = np.random.default_rng(seed)
@@ -79,7 +81,7 @@ def train(X, Y, iters=3000, batch=4096, lr=1e-3, seed=5, log_every=0, g_max=0.95
         idx = torch.randint(0, len(Yd), (batch,), device=dev, generator=gen)
         xb, yb = Xd[idx].contiguous(), Yd[idx].contiguous()
         want = log_every and (t % log_every == 0 or t == iters)
-        loss = B.mlp_grad(W, xb, yb, G, work, with_loss=bool(want))
+        loss = B.mlp_grad(W, xb, yb, G, work, with_loss=bool(want), bf16=bf16)
         if want:
             losses.append((t, loss))
         B.mlp_adam(W, G, M, V, t, lr)

@@ -476,11 +476,284 @@ __global__ void __launch_bounds__(kThreads) k_closure_sample(Lvl2 L2, const T3* 
   Y[x] = (float)qb3[x];
 }
 
+// ---- BF16 training step on the MFMA (FP32 master weights) ----
+// One workgroup of four waves takes 64 samples, a wave 16 of them as the
+// columns of the BF16 16x16x16 instruction (lane l: A[l%16][4(l/16) + i],
+// B[4(l/16) + i][l%16], accumulator rows 4(l/16) + r of column l%16).  The
+// weights enter as BF16 A fragments (W for the forward pass, W^T for the
+// backward one), the activations and their gradients as BF16 B fragments,
+// every sum in FP32.  A layer's accumulator rows 16 b + 4(l/16) + r are the
+// B rows 16 ks + 4(l/16) + i of the next layer's k-step ks = b, so the
+// forward and backward passes stay in registers; the weight gradients
+// (sums over the samples) take the activations and gradients of a wave
+// through an LDS tile, as A = dH [unit][sample] and B = H [sample][unit].
+// The four waves' sums are added in a fixed order in LDS and each
+// workgroup writes its partial gradient; k_mlp_grad_reduce adds the
+// partials of all workgroups in a fixed order (no atomics).
+typedef short bs4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_rn(float x) {   // round to nearest even
+  const unsigned u = __builtin_bit_cast(unsigned, x);
+  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ bs4 bpack(float a, float b, float c, float d) {
+  return bs4{bf16_rn(a), bf16_rn(b), bf16_rn(c), bf16_rn(d)};
+}
+__device__ __forceinline__ cf4 mfma_b(bs4 a, bs4 b, cf4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+constexpr int kTW = 4;                     // waves per workgroup
+constexpr int kTS = kTW * 16;              // samples per workgroup
+
+struct TrainLds {
+  bs4 w1[4][64];                           // W1 s (rows 16 rb + l%16, inputs 4 g + i)
+  bs4 w2[4][4][64], w3[4][4][64];          // W [row block][k-step][lane]
+  bs4 w2t[4][4][64], w3t[4][4][64];        // W^T
+  float tile[kTW][2][64][17];              // per wave: a gradient and an activation [unit][sample]
+  float acc[64][65];                       // the workgroup's sum of one weight matrix
+  float vec[8][64];                        // sums of b1, b2, b3, W4, then b4, loss
+};
+
+__global__ void __launch_bounds__(kTW * 64) k_mlp_grad_bf16(const float* __restrict__ W,
+                                                            const float* __restrict__ X,
+                                                            const float* __restrict__ T, int n,
+                                                            float* __restrict__ part,
+                                                            float* __restrict__ lossp) {
+  extern __shared__ char lds_raw[];
+  TrainLds& S = *reinterpret_cast<TrainLds*>(lds_raw);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4, col = lane & 15;
+  const float sc = W[0], gmax = W[1];
+  // weight fragments, BF16
+  for (int x = tid; x < 4 * 64; x += blockDim.x) {
+    const int rb = x >> 6, l = x & 63, row = 16 * rb + (l & 15);
+    float v[4];
+    for (int i = 0; i < 4; ++i) {
+      const int k = 4 * (l >> 4) + i;
+      v[i] = k < kIn ? sc * W[oW1 + row * kIn + k] : 0.f;
+    }
+    S.w1[rb][l] = bpack(v[0], v[1], v[2], v[3]);
+  }
+  for (int x = tid; x < 16 * 64; x += blockDim.x) {
+    const int rb = x >> 8, ks = (x >> 6) & 3, l = x & 63;
+    const int row = 16 * rb + (l & 15), k0 = 16 * ks + 4 * (l >> 4);
+    const float* w2 = W + oW2;
+    const float* w3 = W + oW3;
+    S.w2[rb][ks][l] = bpack(w2[row * kH + k0], w2[row * kH + k0 + 1], w2[row * kH + k0 + 2],
+                            w2[row * kH + k0 + 3]);
+    S.w3[rb][ks][l] = bpack(w3[row * kH + k0], w3[row * kH + k0 + 1], w3[row * kH + k0 + 2],
+                            w3[row * kH + k0 + 3]);
+    S.w2t[rb][ks][l] = bpack(w2[k0 * kH + row], w2[(k0 + 1) * kH + row], w2[(k0 + 2) * kH + row],
+                             w2[(k0 + 3) * kH + row]);
+    S.w3t[rb][ks][l] = bpack(w3[k0 * kH + row], w3[(k0 + 1) * kH + row], w3[(k0 + 2) * kH + row],
+                             w3[(k0 + 3) * kH + row]);
+  }
+  for (int x = tid; x < 8 * 64; x += blockDim.x) (&S.vec[0][0])[x] = 0.f;
+  __syncthreads();
+  // this lane's sample (lanes past n compute on the last one and add nothing)
+  const int s = blockIdx.x * kTS + wv * 16 + col;
+  const bool live = s < n;
+  const int sc_ = live ? s : n - 1;
+  float xin[kIn];
+#pragma unroll
+  for (int k = 0; k < kIn; ++k) xin[k] = X[(size_t)sc_ * kRow + k];
+  const float inv = input_inv_rms(xin);
+  const float rp = X[(size_t)sc_ * kRow + kIn];
+  float xs[16];                              // the scaled inputs (sc folded into W1)
+#pragma unroll
+  for (int k = 0; k < 16; ++k) xs[k] = k < kIn ? inv * xin[k] : 0.f;
+  // ---- forward
+  cf4 h1[4], h2[4], h3[4];
+  {
+    const bs4 bx = bpack(xs[4 * g], xs[4 * g + 1], xs[4 * g + 2], xs[4 * g + 3]);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      cf4 a = mfma_b(S.w1[rb][lane], bx, cf4{0, 0, 0, 0});
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = tanhf(a[r] + W[ob1 + 16 * rb + 4 * g + r]);
+      h1[rb] = a;
+    }
+  }
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+    const cf4* hin = layer == 0 ? h1 : h2;
+    cf4* hout = layer == 0 ? h2 : h3;
+    const float* bias = W + (layer == 0 ? ob2 : ob3);
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      cf4 a = cf4{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const bs4 b = bpack(hin[ks][0], hin[ks][1], hin[ks][2], hin[ks][3]);
+        a = mfma_b(layer == 0 ? S.w2[rb][ks][lane] : S.w3[rb][ks][lane], b, a);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = tanhf(a[r] + bias[16 * rb + 4 * g + r]);
+      hout[rb] = a;
+    }
+  }
+  float y = 0.f;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) y += W[oW4 + 16 * rb + 4 * g + r] * h3[rb][r];
+  y += __shfl_xor(y, 16, 64);
+  y += __shfl_xor(y, 32, 64);
+  y += W[ob4];
+  const float th = tanhf(y);
+  const float e = live ? gmax * th * rp - T[sc_] : 0.f;
+  const float dy = live ? 2.f * e / (float)n * gmax * rp * (1.f - th * th) : 0.f;
+  // ---- backward through the activations
+  cf4 d3[4], d2[4], d1[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      d3[rb][r] = W[oW4 + 16 * rb + 4 * g + r] * dy * (1.f - h3[rb][r] * h3[rb][r]);
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+    const cf4* dout = layer == 0 ? d3 : d2;
+    const cf4* hact = layer == 0 ? h2 : h1;
+    cf4* din = layer == 0 ? d2 : d1;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      cf4 a = cf4{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const bs4 b = bpack(dout[ks][0], dout[ks][1], dout[ks][2], dout[ks][3]);
+        a = mfma_b(layer == 0 ? S.w3t[rb][ks][lane] : S.w2t[rb][ks][lane], b, a);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] *= 1.f - hact[rb][r] * hact[rb][r];
+      din[rb] = a;
+    }
+  }
+  // ---- vector sums over the wave's samples: b1, b2, b3 (the gradients),
+  // W4 (dy h3), b4 (dy) and the squared error; lanes of one group hold the
+  // same rows for 16 samples
+  auto wave_sum16 = [&](float v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    return v;
+  };
+  float bsum[4][4][4];   // [vector][rb][r]
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      bsum[0][rb][r] = wave_sum16(d1[rb][r]);
+      bsum[1][rb][r] = wave_sum16(d2[rb][r]);
+      bsum[2][rb][r] = wave_sum16(d3[rb][r]);
+      bsum[3][rb][r] = wave_sum16(dy * h3[rb][r]);
+    }
+  const float dysum = wave_sum16(g == 0 ? dy : 0.f);
+  const float esum = wave_sum16(g == 0 ? e * e : 0.f);
+  for (int w = 0; w < kTW; ++w) {            // fixed order over the waves
+    if (wv == w && col == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) S.vec[v][16 * rb + 4 * g + r] += bsum[v][rb][r];
+      if (g == 0) {
+        S.vec[4][0] += dysum;
+        S.vec[5][0] += esum;
+      }
+    }
+    __syncthreads();
+  }
+  // ---- weight matrices: dW = sum over samples of dH (unit) x H (unit)
+  float* part_blk = part + (size_t)blockIdx.x * kNW;
+  float (*Tg)[17] = S.tile[wv][0];
+  float (*Th)[17] = S.tile[wv][1];
+#pragma unroll 1
+  for (int m = 0; m < 3; ++m) {              // W3 (d3, h2), W2 (d2, h1), W1 (d1, x)
+    const cf4* dg = m == 0 ? d3 : (m == 1 ? d2 : d1);
+    const cf4* ha = m == 0 ? h2 : h1;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int u = 16 * rb + 4 * g + r;
+        Tg[u][col] = dg[rb][r];
+        Th[u][col] = m == 2 ? (u < 16 ? xs[u] : 0.f) : ha[rb][r];
+      }
+    __syncthreads();
+    // A[row = unit o][k = sample], B[k = sample][col = unit i]
+    cf4 acc[4][4];
+    const int ncb = m == 2 ? 1 : 4;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const bs4 a = bpack(Tg[16 * rb + col][4 * g], Tg[16 * rb + col][4 * g + 1],
+                          Tg[16 * rb + col][4 * g + 2], Tg[16 * rb + col][4 * g + 3]);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        if (cb >= ncb) break;
+        const bs4 b = bpack(Th[16 * cb + col][4 * g], Th[16 * cb + col][4 * g + 1],
+                            Th[16 * cb + col][4 * g + 2], Th[16 * cb + col][4 * g + 3]);
+        acc[rb][cb] = mfma_b(a, b, cf4{0, 0, 0, 0});
+      }
+    }
+    for (int x = tid; x < 64 * 65; x += blockDim.x) (&S.acc[0][0])[x] = 0.f;
+    __syncthreads();
+    for (int w = 0; w < kTW; ++w) {
+      if (wv == w) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb) {
+            if (cb >= ncb) break;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) S.acc[16 * rb + 4 * g + r][16 * cb + col] += acc[rb][cb][r];
+          }
+      }
+      __syncthreads();
+    }
+    if (m == 0) {
+      for (int x = tid; x < kH * kH; x += blockDim.x) part_blk[oW3 + x] = S.acc[x / kH][x % kH];
+    } else if (m == 1) {
+      for (int x = tid; x < kH * kH; x += blockDim.x) part_blk[oW2 + x] = S.acc[x / kH][x % kH];
+    } else {
+      for (int x = tid; x < kH * kIn; x += blockDim.x)
+        part_blk[oW1 + x] = sc * S.acc[x / kIn][x % kIn];
+    }
+    __syncthreads();
+  }
+  for (int x = tid; x < kH; x += blockDim.x) {
+    part_blk[ob1 + x] = S.vec[0][x];
+    part_blk[ob2 + x] = S.vec[1][x];
+    part_blk[ob3 + x] = S.vec[2][x];
+    part_blk[oW4 + x] = S.vec[3][x];
+  }
+  if (tid == 0) {
+    part_blk[ob4] = S.vec[4][0];
+    part_blk[0] = part_blk[1] = 0.f;
+    lossp[blockIdx.x] = S.vec[5][0];
+  }
+}
+
+// G[p] = sum over the workgroups' partial gradients, in workgroup order.
+__global__ void __launch_bounds__(kThreads) k_mlp_grad_reduce(const float* __restrict__ part,
+                                                              int nb, float* __restrict__ G) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kNW) return;
+  float acc = 0.f;
+  for (int b = 0; b < nb; ++b) acc += part[(size_t)b * kNW + p];
+  G[p] = acc;
+}
+
 }  // namespace
 
-// work: H[192][n], dH[192][n], Y[n], dY[n], Th[n], Inv[n], then the loss partials
+// work of the FP32 step: H[192][n], dH[192][n], Y[n], dY[n], Th[n], Inv[n],
+// then the loss partials; of the BF16 step: the workgroups' partial
+// gradients and loss partials.  The buffer serves either.
 constexpr size_t work_floats(int n) {
-  return (size_t)n * (2 * 3 * kH + 4) + (n + kThreads - 1) / kThreads;
+  const size_t f32 = (size_t)n * (2 * 3 * kH + 4) + (n + kThreads - 1) / kThreads;
+  const size_t b16 = (size_t)((n + 63) / 64) * (kNW + 1);
+  return f32 > b16 ? f32 : b16;
 }
 size_t mlp_work_floats(int n) { return work_floats(n); }
 
@@ -549,6 +822,30 @@ hipError_t mlp_adam(float* W, const float* G, float* M, float* V, int t, float l
   hipLaunchKernelGGL(k_adam, dim3((kNW + kThreads - 1) / kThreads), dim3(kThreads), 0, st, W, G, M,
                      V, t, lr, b1, b2, eps);
   return hipGetLastError();
+}
+
+// BF16 training step: the workgroups' partial gradients [nb][kNW], then
+// the loss partials [nb], at the start of the work buffer (nb = n / 64
+// rounded up; fewer floats than the FP32 step's work for any n >= 1).
+hipError_t mlp_grad_bf16(const float* W, const float* X, const float* T, int n, float* G,
+                         float* work, hipStream_t st) {
+  if (n <= 0) return hipErrorInvalidValue;
+  const int nb = (n + kTS - 1) / kTS;
+  static_assert(kTS == 64, "work_floats counts 64 samples per workgroup");
+  float* part = work;
+  float* lossp = work + (size_t)nb * kNW;
+  const size_t lds = sizeof(TrainLds);
+  static_assert(sizeof(TrainLds) <= 160 * 1024, "LDS");
+  hipError_t e = kernel_setup((const void*)k_mlp_grad_bf16, kTW * 64, lds, nullptr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_grad_bf16, dim3(nb), dim3(kTW * 64), lds, st, W, X, T, n, part, lossp);
+  hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((kNW + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     st, part, nb, G);
+  return hipGetLastError();
+}
+
+const float* mlp_loss_partials_bf16(const float* work, int n) {
+  return work + (size_t)((n + kTS - 1) / kTS) * kNW;
 }
 
 const float* mlp_loss_partials(const float* work, int n) {

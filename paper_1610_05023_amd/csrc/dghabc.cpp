@@ -1459,6 +1459,25 @@ dgh_status dgh_mlp_grad(const float* W, const float* X, const float* T, int n, f
   return DGH_OK;
 }
 
+dgh_status dgh_mlp_grad_bf16(const float* W, const float* X, const float* T, int n, float* G,
+                             float* work, double* loss, void* stream) {
+  if (!W || !X || !T || !G || !work || n <= 0) return DGH_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dgh::mlp_grad_bf16(W, X, T, n, G, work, st) != hipSuccess) return DGH_EHIP;
+  if (loss) {
+    const int nb = (n + 63) / 64;
+    std::vector<float> part(nb);
+    if (hipMemcpyAsync(part.data(), dgh::mlp_loss_partials_bf16(work, n), nb * sizeof(float),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return DGH_EHIP;
+    double sum = 0.0;
+    for (float v : part) sum += v;
+    *loss = sum / n;
+  }
+  return DGH_OK;
+}
+
 dgh_status dgh_mlp_grad_static(const float* W, const float* X, const float* T, int n, float* G,
                                double* loss, void* stream) {
   static_assert(dgh::kMlpStaticBatch == DGH_MLP_STATIC_BATCH, "header and library agree");

@@ -228,6 +228,9 @@ const float* mlp_loss_partials(const float* work, int n);
 hipError_t mlp_forward(const float* W, const float* X, int n, float* Y, hipStream_t st);
 hipError_t mlp_grad(const float* W, const float* X, const float* T, int n, float* G, float* work,
                     hipStream_t st);
+hipError_t mlp_grad_bf16(const float* W, const float* X, const float* T, int n, float* G,
+                         float* work, hipStream_t st);
+const float* mlp_loss_partials_bf16(const float* work, int n);
 hipError_t mlp_adam(float* W, const float* G, float* M, float* V, int t, float lr, float b1,
                     float b2, float eps, hipStream_t st);
 hipError_t launch_closure(const Lvl2& L2, const float* W, const void* q3, int q3f32, int np3,
