@@ -54,12 +54,16 @@ __device__ __forceinline__ Rsrc rsrc(const void* p, unsigned bytes) {
 __device__ __forceinline__ float fld(Rsrc r, unsigned voff, unsigned soff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
-// streaming (non-temporal) load and store: read or written once per stage
+// streaming (non-temporal) load: read once per stage
 __device__ __forceinline__ float fldn(Rsrc r, unsigned voff, unsigned soff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 2));
 }
-__device__ __forceinline__ void fstn(Rsrc r, unsigned voff, unsigned soff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 2);
+// store of the new state and residual, without the streaming hint: an FP32
+// node row of a tile is 64 bytes, half a cache line, and streaming stores
+// of the two halves reached HBM as separate partial writes (1.40 times the
+// bytes at N = 5; plain stores write each line once)
+__device__ __forceinline__ void fst(Rsrc r, unsigned voff, unsigned soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
 
 template <int N>
@@ -259,8 +263,8 @@ __device__ __forceinline__ void tile_f32(const Lvl3& L, const float* __restrict_
 #pragma unroll
         for (int fl = 0; fl < 4; ++fl) {
           const float rr = A * ro[r][fl] + dt * rhs[fl];
-          fstn(Rr, o, fl * FS, rr);
-          fstn(Rn, o, fl * FS, qv[r][fl] + B * rr);
+          fst(Rr, o, fl * FS, rr);
+          fst(Rn, o, fl * FS, qv[r][fl] + B * rr);
         }
       }
     }
@@ -606,8 +610,8 @@ __device__ __forceinline__ void tile_f32_dma(const Lvl3& L, const float* __restr
 #pragma unroll
       for (int fl = 0; fl < 4; ++fl) {
         const float rr = A * rv[b][r][fl] + dt * rhs[fl];
-        fstn(Rr, o, fl * FS, rr);
-        fstn(Rn, o, fl * FS, qd[b][r][fl] + B * rr);
+        fst(Rr, o, fl * FS, rr);
+        fst(Rn, o, fl * FS, qd[b][r][fl] + B * rr);
       }
     }
   }
@@ -990,8 +994,8 @@ __device__ __forceinline__ void tile_bf16(const Lvl3& L, const float* __restrict
 #pragma unroll
         for (int fl = 0; fl < 4; ++fl) {
           const float rr = A * ro[r][fl] + dt * rhs[fl];
-          fstn(Rr, o, fl * FS, rr);
-          fstn(Rn, o, fl * FS, qv[r][fl] + B * rr);
+          fst(Rr, o, fl * FS, rr);
+          fst(Rn, o, fl * FS, qv[r][fl] + B * rr);
         }
       }
     }
