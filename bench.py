@@ -181,7 +181,11 @@ def run_reflection(args):
     the network's history of step ends spans the same time as in use.
     --teacher small uses the test's small recipe (six pulses on 8^3 x 6
     tets, c = 1); --teacher case uses four pulses on this case's own mesh
-    and medium, centred away from the source."""
+    and medium, centred away from the source; --teacher config1 uses 200
+    runs of the 8^3 x 6-tet parity case (N = 3, HABC P = 3, rho = c = 1,
+    Gaussian pulse of width 0.05) at seeded random centres, each at that
+    case's own time step to t = 1, and trains with the BF16 gradient
+    (FP32 master weights)."""
     import numpy as np
     import torch
     import workloads as w
@@ -226,9 +230,21 @@ def run_reflection(args):
     if args.closure:
         from paper_1610_05023_amd.closure import teacher_samples, train
         t0 = time.perf_counter()
-        print(f"[bench] reflection: training the closure ({args.teacher} teacher runs, "
-              "2,500 Adam steps)", file=sys.stderr, flush=True)
-        if args.teacher == "small":
+        print(f"[bench] reflection: training the closure ({args.teacher} teacher runs)",
+              file=sys.stderr, flush=True)
+        train_kw = dict(iters=2500, batch=4096, lr=1e-3, seed=5)
+        if args.teacher == "config1":
+            c1 = w.config("1")
+            VXt, Et = w.kuhn_mesh(c1.n)
+            Kt = Et.shape[0]
+            steps1 = int(round(1.0 / c1.dt))
+            every = int(round(0.04 / c1.dt))
+            X, Y = teacher_samples(VXt, Et, c1.N, c1.P, np.ones(Kt), np.ones(Kt), c1.dt,
+                                   np.random.default_rng(11).uniform(0.25, 0.75, size=(200, 3)),
+                                   c1.extra["width"], steps=steps1, every=every,
+                                   start=int(round(0.2 / c1.dt)), tau=tau)
+            train_kw = dict(iters=6000, batch=16384, lr=1e-3, seed=5, bf16=True)
+        elif args.teacher == "small":
             nt = 8
             VXt, Et = w.kuhn_mesh(nt)
             Kt = Et.shape[0]
@@ -245,7 +261,10 @@ def run_reflection(args):
             X, Y = teacher_samples(VX, E, N, 6, rho, c, dt,
                                    np.random.default_rng(7).uniform(0.25, 0.75, size=(4, 3)),
                                    0.08, steps=steps, every=400, start=400, tau=tau)
-        wts, _ = train(X, Y, iters=2500, batch=4096, lr=1e-3, seed=5)
+        wts, losses = train(X, Y, log_every=train_kw["iters"] // 4, **train_kw)
+        print(f"[bench] reflection: losses {[(t, f'{l:.3e}') for t, l in losses]}, target "
+              f"mean square {float(np.mean(Y.astype(np.float64) ** 2)):.3e}",
+              file=sys.stderr, flush=True)
         print(f"[bench] reflection: closure trained on {len(Y)} samples in "
               f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         inner["closure"] = run(VX, E, rho, c, 0, "closure", closure=wts)
@@ -263,6 +282,7 @@ def run_reflection(args):
                                   "against the doubled domain [-0.5, 1.5]^3 (80^3 x 6 tets, "
                                   "HABC P=6), t = 0.45",
                       "steps": steps, "dt": dt,
+                      "teacher": args.teacher if args.closure else None,
                       "relative_l2_error_q3_unit_cube": err,
                       "reference_q3_norm": float(np.linalg.norm(r))}))
 
@@ -403,9 +423,10 @@ def main():
                     help="P = 0 with the learned boundary closure (layered workload: seeded "
                          "random weights, the cost does not depend on them; reflection "
                          "workload: trained first, then evaluated)")
-    ap.add_argument("--teacher", choices=["small", "case"], default="small",
-                    help="reflection --closure: teacher runs of the small recipe (8^3, c = 1) "
-                         "or on the case's own mesh and medium")
+    ap.add_argument("--teacher", choices=["small", "case", "config1"], default="small",
+                    help="reflection --closure: teacher runs of the small recipe (8^3, c = 1), "
+                         "on the case's own mesh and medium, or 200 runs of the 8^3 parity "
+                         "case (BF16 training)")
     ap.add_argument("--candidate", type=int, default=None,
                     help="force a launch tuning candidate of the 3D level")
     ap.add_argument("--tuning-cache", default=None,
