@@ -185,10 +185,10 @@ dgh_status dgh_set_graph(dgh_ctx* ctx, int enable);
 
 /* Launch tuning of the 3D level (the counterpart of the paper's choice of
  * elements per block, Section 4.2).  Candidates (dgh_tuning_count: 12 for
- * FP64 with N <= 4 and FP32 with N <= 5, else 6) are (kernel * 2 + order)
- * * 3 + grid: kernel 0 holds a whole tile on chip where it fits (else it
- * is the one kernel there is: register streaming, and for the BF16 variant
- * its own kernel), kernel 1 streams it through registers; order 0 gives
+ * FP64 with N <= 4 and the FP32 and BF16 variants with N <= 5, else 6) are
+ * (kernel * 2 + order) * 3 + grid: kernel 0 holds a whole tile on chip
+ * where it fits (else it is the one kernel there is, register streaming),
+ * kernel 1 streams it through registers; order 0 gives
  * each of the 8 XCDs a contiguous range of tiles, order 1 deals tiles
  * round-robin over all workgroups; grid 0, 1, 2 launches 8, 6 or 4 eighths
  * of the workgroups that fit on the device at once, each walking more

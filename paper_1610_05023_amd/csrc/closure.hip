@@ -492,12 +492,15 @@ __global__ void __launch_bounds__(kThreads) k_closure_sample(Lvl2 L2, const T3* 
 // partials of all workgroups in a fixed order (no atomics).
 typedef short bs4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ short bf16_rn(float x) {   // round to nearest even
-  const unsigned u = __builtin_bit_cast(unsigned, x);
-  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
+// four FP32 -> BF16, round to nearest even: two v_cvt_pk_bf16_f32
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+typedef unsigned u2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ bs4 bpack(float a, float b, float c, float d) {
-  return bs4{bf16_rn(a), bf16_rn(b), bf16_rn(c), bf16_rn(d)};
+  const bf2 lo = __builtin_convertvector(fl2{a, b}, bf2);
+  const bf2 hi = __builtin_convertvector(fl2{c, d}, bf2);
+  return __builtin_bit_cast(bs4,
+                            u2{__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi)});
 }
 __device__ __forceinline__ cf4 mfma_b(bs4 a, bs4 b, cf4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);

@@ -1122,12 +1122,12 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
 
 namespace {
 // tuning candidates: two 3D kernels (tile on chip, register streaming)
-// where the tile fits on chip (FP64 N <= 4, FP32 N <= 5), else one; x two
-// item orders; x three persistent grid sizes (8, 6 or 4 eighths of the
-// resident workgroups); candidate = (kernel * 2 + order) * 3 + grid
+// where the tile fits on chip (FP64 N <= 4, FP32 and BF16 N <= 5), else
+// one; x two item orders; x three persistent grid sizes (8, 6 or 4 eighths
+// of the resident workgroups); candidate = (kernel * 2 + order) * 3 + grid
 constexpr int kGrids[3] = {8, 6, 4};
 int tuning_count(const dgh_ctx* c) {
-  const int nmax = c->precision == DGH_FP64 ? 4 : (c->precision == DGH_FP32_MFMA ? 5 : 0);
+  const int nmax = c->precision == DGH_FP64 ? 4 : 5;
   return (c->N <= nmax ? 4 : 2) * 3;
 }
 void apply_tuning(dgh_ctx* c, int candidate) {

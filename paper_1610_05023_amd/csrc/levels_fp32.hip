@@ -794,14 +794,15 @@ __device__ __forceinline__ f4 mfma_bf16(s4 a, s4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// FP32 -> BF16, round to nearest even (finite inputs)
-__device__ __forceinline__ short bf16_rn(float x) {
-  const unsigned u = __builtin_bit_cast(unsigned, x);
-  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
-
+// four FP32 -> BF16, round to nearest even: two v_cvt_pk_bf16_f32
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2f __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ s4 pack4(const float* v) {
-  return s4{bf16_rn(v[0]), bf16_rn(v[1]), bf16_rn(v[2]), bf16_rn(v[3])};
+  const bf2 lo = __builtin_convertvector(fl2{v[0], v[1]}, bf2);
+  const bf2 hi = __builtin_convertvector(fl2{v[2], v[3]}, bf2);
+  return __builtin_bit_cast(
+      s4, u32x2f{__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi)});
 }
 
 template <int N>
@@ -1026,9 +1027,370 @@ __global__ void __launch_bounds__(kWaves3f * 64, Dims3b<N>::kOcc) k_level3_bf16(
     tile_bf16<N>(L, qo, qn, res, qb3, A, B, dt, sh, item, ngrp, smap, smask, sops, lane);
 }
 
+// ------------------------------------------ BF16 contractions, tile on chip ---
+// N <= 5: the BF16 contractions over the tile-on-chip scheme of the FP32
+// kernel (one workgroup of four waves per CU, each wave's next FP32 tile
+// arriving in its LDS buffer by direct loads while it finishes the current
+// one).  With K = 16 a lane's B operand of k-step j is the nodes
+// 16 j + 4 (l/16) + i of its element, read from the LDS copy and rounded to
+// BF16; the exterior traces of faces 0-2 are in flight during the volume
+// term, face 3's during face 0.
+template <int N>
+struct FaceInB {
+  static constexpr int FK = Dims3b<N>::FK;
+  float p[FK][4], u[FK][4], v[FK][4], w[FK][4], rb[FK][4];
+};
+
+template <int N>
+__device__ __forceinline__ void face_fetch_b(FaceInB<N>& x, int f, int code, int e, Rsrc Rq,
+                                             const double* __restrict__ qb3, const int* smap,
+                                             int g) {
+  using D = Dims3b<N>;
+  constexpr int Np = D::Np, Nfp = D::Nfp, FK = D::FK;
+  constexpr unsigned FS = Np * kTile * 4, TS = 4 * FS;
+  const bool inner = code >= 0;
+  const int cb = -1 - code;
+  const bool hb = !inner && (cb & 3) == 0;
+  const int e2 = inner ? (code >> 5) : e;
+  const unsigned nb = (unsigned)(e2 >> 4) * TS + (unsigned)(e2 & 15) * 4;
+  const int mapbase = inner ? ((f * 4 + ((code >> 3) & 3)) * 6 + (code & 7)) * Nfp
+                            : ((f * 4) * 6 + ((cb >> 2) & 7)) * Nfp;
+  const double* qbt = qb3 + (size_t)(hb ? (cb >> 5) : 0) * Nfp;
+#pragma unroll
+  for (int jj = 0; jj < FK; ++jj)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int kc = min(16 * jj + 4 * g + i, Nfp - 1);
+      const int n2 = smap[mapbase + kc];
+      const unsigned oP = nb + (unsigned)n2 * (kTile * 4);
+      x.p[jj][i] = fld(Rq, oP, 0);
+      x.u[jj][i] = fld(Rq, oP, FS);
+      x.v[jj][i] = fld(Rq, oP, 2 * FS);
+      x.w[jj][i] = fld(Rq, oP, 3 * FS);
+      x.rb[jj][i] = (float)qbt[min(n2, Nfp - 1)];
+    }
+}
+
+// One work item whose tile is in buf; fetch_next() issues the direct loads
+// of the next item (if any) once the tile's copy has been read.
+template <int N, class Fetch>
+__device__ __forceinline__ void tile_bf16_dma(const Lvl3& L, const float* __restrict__ qo,
+                                              float* __restrict__ qn, float* __restrict__ res,
+                                              const double* __restrict__ qb3, float A, float B,
+                                              float dt, const Shots& sh, long long item,
+                                              Fetch fetch_next, int ngrp, const int* smap,
+                                              const int* smask, const s4* sops, char* buf,
+                                              int lane) {
+  using D = Dims3b<N>;
+  using BR = BufF<N>;
+  constexpr int Np = D::Np, Nfp = D::Nfp, RB = D::RB, FK = D::FK;
+  constexpr unsigned FS = Np * kTile * 4;   // bytes between two fields of a tile
+  constexpr unsigned TS = 4 * FS;           // bytes per tile
+  const int shot = (int)(item / ngrp);
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int tile = (int)(item - (long long)shot * ngrp) * kWavesF + wv;
+  // the tile's direct loads have landed: vector memory operations complete in
+  // order and the previous tile issued 32 RB stores after them
+  constexpr int kVm = 32 * RB < 63 ? 32 * RB : 63;
+  __builtin_amdgcn_s_waitcnt((kVm & 15) | ((kVm >> 4) << 14) | (7 << 4) | (15 << 8));
+  if (tile >= L.ntile) {
+    __builtin_amdgcn_s_waitcnt(0);
+    fetch_next();
+    __builtin_amdgcn_s_waitcnt(0);
+    return;
+  }
+  const float* qos = qo + shot * sh.st3;
+  float* qns = qn + shot * sh.st3;
+  float* ress = res + shot * sh.st3;
+  const double* qbs = qb3 + shot * sh.stb3;
+  const int es = lane & 15, g = lane >> 4;
+  const s4* frag = sops + lane;
+  const s4* fragL = frag + 3 * RB * RB * 64;
+  const int e = tile * kTile + es;
+  const unsigned nbytes = (unsigned)L.ntile * TS;
+  const Rsrc Rq = rsrc(qos, nbytes), Rn = rsrc(qns, nbytes), Rr = rsrc(ress, nbytes);
+  const unsigned tb = (unsigned)tile * TS + (unsigned)es * 4;   // this lane's element
+  const float* bq = reinterpret_cast<const float*>(buf) + es;    // [field][node][16]
+  const double* bg = reinterpret_cast<const double*>(buf + BR::GEO) + es;
+  const double* bz = reinterpret_cast<const double*>(buf + BR::ZN) + es;
+  const int* bc = reinterpret_cast<const int*>(buf + BR::NBR) + es;
+  int fcode[4];
+  float fz[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    fcode[f] = bc[f * kTile];
+    fz[f] = (float)bz[f * kTile];
+  }
+  FaceInB<N> fb[4];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) face_fetch_b<N>(fb[f], f, fcode[f], e, Rq, qbs, smap, g);
+  const float rx = (float)bg[0 * kTile], ry = (float)bg[1 * kTile], rz = (float)bg[2 * kTile];
+  const float sx = (float)bg[3 * kTile], sy = (float)bg[4 * kTile], sz = (float)bg[5 * kTile];
+  const float tx = (float)bg[6 * kTile], ty = (float)bg[7 * kTile], tz = (float)bg[8 * kTile];
+  const float irho = (float)bg[9 * kTile], Kb = (float)bg[10 * kTile], Z = (float)bg[11 * kTile];
+
+  // ---- volume: one k-step of 16 nodes at a time, B operands from the copy
+  f4 dpr[RB], dps[RB], dpt[RB], dv[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) dpr[b] = dps[b] = dpt[b] = dv[b] = f4{0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    float p[4], fr[4], fs[4], ft[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int n = min(16 * j + 4 * g + i, Np - 1);
+      const float u = bq[(Np + n) * kTile], v = bq[(2 * Np + n) * kTile],
+                  w = bq[(3 * Np + n) * kTile];
+      p[i] = bq[n * kTile];
+      fr[i] = rx * u + ry * v + rz * w;
+      fs[i] = sx * u + sy * v + sz * w;
+      ft[i] = tx * u + ty * v + tz * w;
+    }
+    const s4 bp = pack4(p), br = pack4(fr), bs = pack4(fs), bt = pack4(ft);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const s4 ar = frag[((0 * RB + b) * RB + j) * 64];
+      const s4 as = frag[((1 * RB + b) * RB + j) * 64];
+      const s4 at = frag[((2 * RB + b) * RB + j) * 64];
+      dpr[b] = mfma_bf16(ar, bp, dpr[b]);
+      dps[b] = mfma_bf16(as, bp, dps[b]);
+      dpt[b] = mfma_bf16(at, bp, dpt[b]);
+      dv[b] = mfma_bf16(ar, br, dv[b]);
+      dv[b] = mfma_bf16(as, bs, dv[b]);
+      dv[b] = mfma_bf16(at, bt, dv[b]);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < RB; ++b) dv[b] *= -Kb;
+  f4* rp = dv;
+
+  // ---- surface (as in tile_bf16); own traces from the LDS copy
+  float rv[RB][4][4], qd[RB][4][4], own3[FK][4][4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    __builtin_amdgcn_sched_barrier(0);
+    if (f == 0) {
+      face_fetch_b<N>(fb[3], 3, fcode[3], e, Rq, qbs, smap, g);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (f == 1) {
+      // the residual of this tile at the update's rows
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const unsigned o = tb + (unsigned)min(16 * b + 4 * g + r, Np - 1) * (kTile * 4);
+#pragma unroll
+          for (int fl = 0; fl < 4; ++fl) rv[b][r][fl] = fldn(Rr, o, fl * FS);
+        }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (f == 3) {
+      // the last reads of the copy (face 3's own traces, the update's q),
+      // then the next tile's direct loads
+#pragma unroll
+      for (int jj = 0; jj < FK; ++jj)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int n = smask[3 * Nfp + min(16 * jj + 4 * g + i, Nfp - 1)];
+#pragma unroll
+          for (int fl = 0; fl < 4; ++fl) own3[jj][i][fl] = bq[(fl * Np + n) * kTile];
+        }
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int n = min(16 * b + 4 * g + r, Np - 1);
+#pragma unroll
+          for (int fl = 0; fl < 4; ++fl) qd[b][r][fl] = bq[(fl * Np + n) * kTile];
+        }
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): every LDS read returned
+      __builtin_amdgcn_sched_barrier(0);
+      fetch_next();
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const FaceInB<N>& x = fb[f];
+    const float cr = f == 2 ? 1.f : (f == 3 ? -1.f : 0.f);
+    const float cs = f == 2 ? 1.f : (f == 1 ? -1.f : 0.f);
+    const float ct = f == 2 ? 1.f : (f == 0 ? -1.f : 0.f);
+    float nx = cr * rx + cs * sx + ct * tx;
+    float ny = cr * ry + cs * sy + ct * ty;
+    float nz = cr * rz + cs * sz + ct * tz;
+    const float fsc = sqrtf(nx * nx + ny * ny + nz * nz);
+    const float inv = 1.f / fsc;
+    nx *= inv;
+    ny *= inv;
+    nz *= inv;
+    const int code = fcode[f];
+    const float ZP = fz[f];
+    const bool inner = code >= 0;
+    const int cb = -1 - code;
+    const bool hb = !inner && (cb & 3) == 0;
+    const bool dir = !inner && (cb & 3) == 2;
+    const float iZ = 1.f / (Z + ZP);
+    const float aM = ZP * iZ, aP = Z * iZ, bZ = Z * aM;
+    const float cP = fsc * Kb;
+#pragma unroll
+    for (int jj = 0; jj < FK; ++jj) {
+      float fp[4], fu[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float pM, uM, vM, wM;
+        if (f == 3) {
+          pM = own3[jj][i][0];
+          uM = own3[jj][i][1];
+          vM = own3[jj][i][2];
+          wM = own3[jj][i][3];
+        } else {
+          const int n = smask[f * Nfp + min(16 * jj + 4 * g + i, Nfp - 1)];
+          pM = bq[n * kTile];
+          uM = bq[(Np + n) * kTile];
+          vM = bq[(2 * Np + n) * kTile];
+          wM = bq[(3 * Np + n) * kTile];
+        }
+        const float pP = x.p[jj][i], uP = x.u[jj][i], vP = x.v[jj][i], wP = x.w[jj][i];
+        const float unM = nx * uM + ny * vM + nz * wM;
+        const float unP = nx * uP + ny * vP + nz * wP;
+        const float pG = inner ? pP : (dir ? -pM : (hb ? 2.f * x.rb[jj][i] : 0.f));
+        const float uG = inner ? unP : (dir ? unM : 0.f);
+        const float pF = aM * pM + aP * pG + bZ * (unM - uG);
+        const float unF = iZ * (pM - pG) + aP * unM + aM * uG;
+        fp[i] = cP * (unM - unF);
+        fu[i] = pM - pF;
+      }
+      const s4 bfp = pack4(fp), bfu = pack4(fu);
+      const s4* fl = fragL + (f * FK + jj) * 64;
+      if (f == 2) {
+        float nfu[4] = {-fu[0], -fu[1], -fu[2], -fu[3]};
+        const s4 bnu = pack4(nfu);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          const s4 a = fl[b * 4 * FK * 64];
+          rp[b] = mfma_bf16(a, bfp, rp[b]);
+          dpr[b] = mfma_bf16(a, bnu, dpr[b]);
+          dps[b] = mfma_bf16(a, bnu, dps[b]);
+          dpt[b] = mfma_bf16(a, bnu, dpt[b]);
+        }
+      } else {
+        f4* G = f == 0 ? dpt : (f == 1 ? dps : dpr);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          const s4 a = fl[b * 4 * FK * 64];
+          rp[b] = mfma_bf16(a, bfp, rp[b]);
+          G[b] = mfma_bf16(a, bfu, G[b]);
+        }
+      }
+    }
+  }
+
+  // point source on its element (a uniform branch only that wave takes)
+  {
+    const double* sp = sh.srcp + 4 * shot;
+    const bool src = (double)e == sp[0];
+    if (__builtin_amdgcn_read_exec() & __ballot(src)) {
+      const double trr = stage_time(sh) - sp[2], arr = M_PI * sp[1] * trr;
+      const float src_s = (float)(sp[3] * trr * exp(-arr * arr));
+      const double* src_w = sh.srcw + (size_t)shot * Np;
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (src) rp[b][r] += (float)src_w[min(16 * b + 4 * g + r, Np - 1)] * src_s;
+    }
+  }
+
+  // ---- LSRK update: 32 RB stores, every lane issuing them (a lane without
+  // a row stores past the end of the resource, which the hardware drops)
+  __builtin_amdgcn_sched_barrier(0);
+  const bool live = irho != 0.f;
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int n = 16 * b + 4 * g + r;
+      const unsigned o = (live && n < Np) ? tb + (unsigned)n * (kTile * 4) : 0xFFFFFFF8u;
+      const float a = dpr[b][r], bq_ = dps[b][r], c = dpt[b][r];
+      const float rhs[4] = {rp[b][r],
+                            -irho * (rx * a + sx * bq_ + tx * c),
+                            -irho * (ry * a + sy * bq_ + ty * c),
+                            -irho * (rz * a + sz * bq_ + tz * c)};
+#pragma unroll
+      for (int fl = 0; fl < 4; ++fl) {
+        const float rr = A * rv[b][r][fl] + dt * rhs[fl];
+        fst(Rr, o, fl * FS, rr);
+        fst(Rn, o, fl * FS, qd[b][r][fl] + B * rr);
+      }
+    }
+  }
+}
+
+// LDS of the tile-on-chip BF16 kernel: face-node tables, the BF16 operator
+// fragments (8-byte aligned), then the four tile buffers (16-byte aligned)
+template <int N>
+struct LdsB {
+  static constexpr size_t TAB = sizeof(float) * ((4 * Dims3b<N>::Nfp + 96 * Dims3b<N>::Nfp + 1) & ~1);
+  static constexpr size_t BUF = (TAB + (size_t)Dims3b<N>::NFR * 512 + 15) / 16 * 16;
+  static constexpr size_t BYTES = BUF + (size_t)kWavesF * BufF<N>::BYTES;
+};
+
+template <int N>
+__global__ void __launch_bounds__(kWavesF * 64, 1) k_level3_bf16_dma(
+    Lvl3 L, const float* __restrict__ qo, float* __restrict__ qn, float* __restrict__ res,
+    const double* __restrict__ qb3, float A, float B, float dt, Shots sh) {
+  using D = Dims3b<N>;
+  using LB = LdsB<N>;
+  constexpr int Nfp = D::Nfp;
+  extern __shared__ float sfl[];
+  int* smask = reinterpret_cast<int*>(sfl);
+  int* smap = smask + 4 * Nfp;
+  s4* sops = reinterpret_cast<s4*>(reinterpret_cast<char*>(sfl) + LB::TAB);
+  const int lane = threadIdx.x & 63;
+  const int ngrp = (L.ntile + kWavesF - 1) / kWavesF;
+  const XcdRange rg_(ngrp * (long long)sh.n, L.order);
+  char* buf = reinterpret_cast<char*>(sfl) + LB::BUF +
+              __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * BufF<N>::BYTES;
+  if (rg_.lo < rg_.hi) tile_dma_f<N>(L, qo, sh, rg_.lo, ngrp, buf, lane);
+  fill_lds<kWavesF * 64, 4 * Nfp>(smask, L.fmask, threadIdx.x);
+  fill_lds<kWavesF * 64, 96 * Nfp>(smap, L.fmap, threadIdx.x);
+  fill_lds<kWavesF * 64, D::NFR * 64>(reinterpret_cast<unsigned long long*>(sops),
+                                      reinterpret_cast<const unsigned long long*>(L.opsb),
+                                      threadIdx.x);
+  __syncthreads();
+  for (long long it = rg_.lo; it < rg_.hi; it += rg_.step) {
+    const long long nx = it + rg_.step;
+    auto fetch = [&]() {
+      if (nx < rg_.hi) tile_dma_f<N>(L, qo, sh, nx, ngrp, buf, lane);
+    };
+    tile_bf16_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, it, fetch, ngrp, smap, smask, sops, buf,
+                     lane);
+  }
+}
+
+template <int N>
+hipError_t launch3b_dma(const Lvl3& L, const float* qo, float* qn, float* res, const double* qb3,
+                        double A, double B, double dt, const Shots& sh, hipStream_t st) {
+  const size_t lds = LdsB<N>::BYTES;
+  if (sh.n < 1) return hipErrorInvalidValue;
+  const int ngrp = (L.ntile + kWavesF - 1) / kWavesF;
+  int resident = 0;
+  {
+    const hipError_t e =
+        kernel_setup((const void*)(k_level3_bf16_dma<N>), kWavesF * 64, lds, &resident);
+    if (e != hipSuccess) return e;
+  }
+  const long long items = (long long)ngrp * sh.n;
+  const int blocks = grid3(resident, items, L.eighths);
+  hipLaunchKernelGGL(k_level3_bf16_dma<N>, dim3(blocks), dim3(kWavesF * 64), lds, st, L, qo, qn,
+                     res, qb3, (float)A, (float)B, (float)dt, sh);
+  return hipGetLastError();
+}
+
 template <int N>
 hipError_t launch3b(const Lvl3& L, const float* qo, float* qn, float* res, const double* qb3,
                     double A, double B, double dt, const Shots& sh, hipStream_t st) {
+  if constexpr (N <= 5) {   // the tile buffers and fragments fit the LDS up to N = 5
+    if (L.kvar == 0) return launch3b_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+  }
   using D = Dims3b<N>;
   constexpr int Nfp = D::Nfp;
   const size_t lds = sizeof(float) * ((4 * Nfp + 96 * Nfp + 1) & ~1) + (size_t)D::NFR * 512;

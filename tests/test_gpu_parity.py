@@ -452,7 +452,7 @@ def test_graph_replay_equals_eager(precision):
     print(f"[graph] precision {precision}: replayed == eager bitwise", flush=True)
 
 
-@pytest.mark.parametrize("precision,N", [(0, 4), (2, 4), (3, 4), (2, 5)])
+@pytest.mark.parametrize("precision,N", [(0, 4), (2, 4), (3, 4), (2, 5), (3, 5), (3, 6)])
 def test_tuning_candidates_and_autotune(precision, N):
     """Every launch candidate of the 3D level (tile on chip / register
     streaming x XCD ranges / round robin) matches the oracle on a layered
@@ -466,7 +466,7 @@ def test_tuning_candidates_and_autotune(precision, N):
     ref = run_oracle(case, steps, dt)
     s = make_solver(case, precision=precision)
     count = s.tuning_count()
-    assert count == (6 if precision == 3 else 12)
+    assert count == (12 if N <= (4 if precision == 0 else 5) else 6)
     for cand in range(count):
         s.set_state(case["state"])
         s.set_tuning(cand)
