@@ -184,12 +184,16 @@ dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, d
 dgh_status dgh_set_graph(dgh_ctx* ctx, int enable);
 
 /* Launch tuning of the 3D level (the counterpart of the paper's choice of
- * elements per block, Section 4.2).  Candidates (dgh_tuning_count: 12 for
- * FP64 with N <= 4 and the FP32 and BF16 variants with N <= 5, else 6) are
- * (kernel * 2 + order) * 3 + grid: kernel 0 holds a whole tile on chip
- * where it fits (else it is the one kernel there is, register streaming),
- * kernel 1 streams it through registers; order 0 gives
- * each of the 8 XCDs a contiguous range of tiles, order 1 deals tiles
+ * elements per block, Section 4.2).  Candidates (dgh_tuning_count: 18 for
+ * FP64 with N <= 4 and the FP32 and BF16 variants with N <= 5, else 12)
+ * are (kernel * 2 + order) * 3 + grid.  Where the tile fits on chip,
+ * kernel 0 holds a whole tile of 16 elements per wave on chip (four waves
+ * per workgroup), kernels 1 and 2 stream it through registers with 4 or 8
+ * waves (64 or 128 elements) per workgroup; elsewhere kernels 0 and 1 are
+ * the register-streaming kernel with its default and with the other
+ * number of waves (the default is 8 for FP64 at N = 5 and for the FP32
+ * and BF16 variants at N = 6, else 4).  Order 0
+ * gives each of the 8 XCDs a contiguous range of tiles, order 1 deals tiles
  * round-robin over all workgroups; grid 0, 1, 2 launches 8, 6 or 4 eighths
  * of the workgroups that fit on the device at once, each walking more
  * tiles when there are fewer.  Every candidate computes the same step.

@@ -526,6 +526,13 @@ hipError_t upload(dgh_ctx* c, const Region& r, const V& v) {
   return h2d(c, c->ws + r.off, v.data(), b);
 }
 
+// register-streaming 3D kernel: 8 waves per workgroup where it is the
+// default kernel with its operators in LDS (FP64 at N = 5, the FP32 and BF16
+// variants at N = 6: two waves per SIMD share them), else 4
+int default_waves(const dgh_ctx* c) {
+  return (c->precision == DGH_FP64 ? c->N == 5 : c->N == 6) ? 8 : 4;
+}
+
 void fill_levels(dgh_ctx* c) {
   const dgh::Mesh& m = c->mesh;
   const Layout& L = c->lay;
@@ -533,6 +540,7 @@ void fill_levels(dgh_ctx* c) {
   a.K = m.K;
   a.ntile = c->ntile;
   if (a.eighths == 0) a.eighths = 8;   // the whole resident grid unless tuned
+  if (a.waves == 0) a.waves = default_waves(c);
   a.N = m.N;
   a.Np = m.tet.Np;
   a.Nfp = m.tet.Nfp;
@@ -1121,17 +1129,24 @@ dgh_status dgh_step(dgh_ctx* c, int n_steps, double dt, double t_start) {
 }
 
 namespace {
-// tuning candidates: two 3D kernels (tile on chip, register streaming)
-// where the tile fits on chip (FP64 N <= 4, FP32 and BF16 N <= 5), else
-// one; x two item orders; x three persistent grid sizes (8, 6 or 4 eighths
-// of the resident workgroups); candidate = (kernel * 2 + order) * 3 + grid
+// tuning candidates: three 3D kernels where the tile fits on chip (FP64
+// N <= 4, FP32 and BF16 N <= 5): tile on chip, register streaming with 4
+// and with 8 waves (64 or 128 elements) per workgroup; else the two
+// register-streaming ones, the default first; x two item orders; x three
+// persistent grid sizes (8, 6 or 4 eighths of the resident workgroups);
+// candidate = (kernel * 2 + order) * 3 + grid
 constexpr int kGrids[3] = {8, 6, 4};
-int tuning_count(const dgh_ctx* c) {
-  const int nmax = c->precision == DGH_FP64 ? 4 : 5;
-  return (c->N <= nmax ? 4 : 2) * 3;
-}
+bool tile_on_chip(const dgh_ctx* c) { return c->N <= (c->precision == DGH_FP64 ? 4 : 5); }
+int tuning_count(const dgh_ctx* c) { return (tile_on_chip(c) ? 3 : 2) * 6; }
 void apply_tuning(dgh_ctx* c, int candidate) {
-  c->L3.kvar = (candidate / 3) >> 1;
+  const int kern = candidate / 6, dw = default_waves(c);
+  if (tile_on_chip(c)) {
+    c->L3.kvar = kern == 0 ? 0 : 1;
+    c->L3.waves = kern == 0 ? dw : (kern == 1 ? 4 : 8);
+  } else {
+    c->L3.kvar = 1;
+    c->L3.waves = kern == 0 ? dw : 12 - dw;
+  }
   c->L3.order = (candidate / 3) & 1;
   c->L3.eighths = kGrids[candidate % 3];
 }
@@ -1168,7 +1183,8 @@ dgh_status dgh_autotune(dgh_ctx* c, int launches, int* best, double* ms) {
   hipEvent_t e0, e1;
   HIPCHECK(c, hipEventCreate(&e0));
   HIPCHECK(c, hipEventCreate(&e1));
-  const int keep_kvar = c->L3.kvar, keep_order = c->L3.order, keep_eighths = c->L3.eighths;
+  const int keep_kvar = c->L3.kvar, keep_order = c->L3.order, keep_eighths = c->L3.eighths,
+            keep_waves = c->L3.waves;
   double tbest = 0.0;
   int ibest = -1;
   hipError_t err = hipSuccess;
@@ -1199,6 +1215,7 @@ dgh_status dgh_autotune(dgh_ctx* c, int launches, int* best, double* ms) {
     c->L3.kvar = keep_kvar;
     c->L3.order = keep_order;
     c->L3.eighths = keep_eighths;
+    c->L3.waves = keep_waves;
     return hipfail(c, err, "autotune");
   }
   apply_tuning(c, ibest);

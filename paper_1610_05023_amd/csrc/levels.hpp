@@ -60,7 +60,8 @@ struct Lvl3 {
   const double* geo;
   const double* zn;
   const int* nbr;
-  int kvar;    // FP64 3D kernel for N <= 4: 0 tile on chip, 1 register-streaming
+  int kvar;    // 3D kernel where the tile fits on chip: 0 tile on chip, 1 register-streaming
+  int waves;   // register-streaming kernels: waves (tiles of 16 elements) per workgroup, 4 or 8
   int order;   // work items: 0 XCD-contiguous ranges, 1 round-robin over blocks
   int eighths; // persistent grid: this many eighths of the resident workgroups
 };

@@ -22,7 +22,9 @@ namespace dgh {
 
 namespace {
 
-constexpr int kWaves3f = 4;   // waves (tiles) per workgroup
+// waves (tiles) per workgroup of the register-streaming kernels: W = 4 or
+// 8 (Lvl3::waves, a tuning axis); with 8 the registers are sized for two
+// waves per SIMD (256 each)
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -66,7 +68,7 @@ __device__ __forceinline__ void fst(Rsrc r, unsigned voff, unsigned soff, float 
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
 
-template <int N>
+template <int N, int W>
 __device__ __forceinline__ void tile_f32(const Lvl3& L, const float* __restrict__ qo,
                                          float* __restrict__ qn, float* __restrict__ res,
                                          const double* __restrict__ qb3, float A, float B,
@@ -78,7 +80,7 @@ __device__ __forceinline__ void tile_f32(const Lvl3& L, const float* __restrict_
   constexpr unsigned FS = Np * kTile * 4;   // bytes between two fields of a tile
   constexpr unsigned TS = 4 * FS;           // bytes per tile
   const int shot = (int)(item / ngrp);
-  const int tile = (int)(item - (long long)shot * ngrp) * kWaves3f + (threadIdx.x >> 6);
+  const int tile = (int)(item - (long long)shot * ngrp) * W + (threadIdx.x >> 6);
   if (tile >= L.ntile) return;
   qo += shot * sh.st3;
   qn += shot * sh.st3;
@@ -271,8 +273,8 @@ __device__ __forceinline__ void tile_f32(const Lvl3& L, const float* __restrict_
   }
 }
 
-template <int N>
-__global__ void __launch_bounds__(kWaves3f * 64, Dims3f<N>::kOcc) k_level3_f32(Lvl3 L, const float* __restrict__ qo,
+template <int N, int W>
+__global__ void __launch_bounds__(W * 64, W == 8 ? 1 : Dims3f<N>::kOcc) k_level3_f32(Lvl3 L, const float* __restrict__ qo,
                                                         float* __restrict__ qn,
                                                         float* __restrict__ res,
                                                         const double* __restrict__ qb3, float A,
@@ -283,15 +285,15 @@ __global__ void __launch_bounds__(kWaves3f * 64, Dims3f<N>::kOcc) k_level3_f32(L
   int* smask = reinterpret_cast<int*>(sfl);
   int* smap = smask + 4 * Nfp;
   float* sops = sfl + 4 * Nfp + 96 * Nfp;
-  fill_lds<kWaves3f * 64, 4 * Nfp>(smask, L.fmask, threadIdx.x);
-  fill_lds<kWaves3f * 64, 96 * Nfp>(smap, L.fmap, threadIdx.x);
-  if (D::kLds) fill_lds<kWaves3f * 64, D::NOPS>(sops, L.ops32, threadIdx.x);
+  fill_lds<W * 64, 4 * Nfp>(smask, L.fmask, threadIdx.x);
+  fill_lds<W * 64, 96 * Nfp>(smap, L.fmap, threadIdx.x);
+  if (D::kLds) fill_lds<W * 64, D::NOPS>(sops, L.ops32, threadIdx.x);
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int ngrp = (L.ntile + kWaves3f - 1) / kWaves3f;
+  const int ngrp = (L.ntile + W - 1) / W;
   const XcdRange rg_(ngrp * (long long)sh.n, L.order);
   for (long long item = rg_.lo; item < rg_.hi; item += rg_.step)
-    tile_f32<N>(L, qo, qn, res, qb3, A, B, dt, sh, item, ngrp, smap, smask, sops, lane);
+    tile_f32<N, W>(L, qo, qn, res, qb3, A, B, dt, sh, item, ngrp, smap, smask, sops, lane);
 }
 
 // ------------------------------------------------- FP32, tile on chip ---
@@ -743,28 +745,34 @@ hipError_t launch3f_dma(const Lvl3& L, const float* qo, float* qn, float* res, c
   return hipGetLastError();
 }
 
+template <int N, int W>
+hipError_t launch3f_reg(const Lvl3& L, const float* qo, float* qn, float* res, const double* qb3,
+                        double A, double B, double dt, const Shots& sh, hipStream_t st) {
+  using D = Dims3f<N>;
+  constexpr int Nfp = D::Nfp;
+  const size_t lds = sizeof(float) * (4 * Nfp + 96 * Nfp + (D::kLds ? D::NOPS : 0));
+  const int ngrp = (L.ntile + W - 1) / W;
+  if (sh.n < 1) return hipErrorInvalidValue;
+  int resident = 0;
+  {
+    const hipError_t e = kernel_setup((const void*)(k_level3_f32<N, W>), W * 64, lds, &resident);
+    if (e != hipSuccess) return e;
+  }
+  const long long items = (long long)ngrp * sh.n;
+  const int blocks = grid3(resident, items, L.eighths);
+  hipLaunchKernelGGL((k_level3_f32<N, W>), dim3(blocks), dim3(W * 64), lds, st, L, qo, qn, res,
+                     qb3, (float)A, (float)B, (float)dt, sh);
+  return hipGetLastError();
+}
+
 template <int N>
 hipError_t launch3f(const Lvl3& L, const float* qo, float* qn, float* res, const double* qb3,
                     double A, double B, double dt, const Shots& sh, hipStream_t st) {
   if constexpr (N <= 5) {   // the tile buffers and fragments fit the LDS up to N = 5
     if (L.kvar == 0) return launch3f_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, st);
   }
-  using D = Dims3f<N>;
-  constexpr int Nfp = D::Nfp;
-  const size_t lds = sizeof(float) * (4 * Nfp + 96 * Nfp + (D::kLds ? D::NOPS : 0));
-  const int ngrp = (L.ntile + kWaves3f - 1) / kWaves3f;
-  if (sh.n < 1) return hipErrorInvalidValue;
-  int resident = 0;
-  {
-    const hipError_t e =
-        kernel_setup((const void*)(k_level3_f32<N>), kWaves3f * 64, lds, &resident);
-    if (e != hipSuccess) return e;
-  }
-  const long long items = (long long)ngrp * sh.n;
-  const int blocks = grid3(resident, items, L.eighths);
-  hipLaunchKernelGGL(k_level3_f32<N>, dim3(blocks), dim3(kWaves3f * 64), lds, st, L, qo, qn, res,
-                     qb3, (float)A, (float)B, (float)dt, sh);
-  return hipGetLastError();
+  if (L.waves == 8) return launch3f_reg<N, 8>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+  return launch3f_reg<N, 4>(L, qo, qn, res, qb3, A, B, dt, sh, st);
 }
 
 // ------------------------------------------------ BF16 contractions ---
@@ -805,7 +813,7 @@ __device__ __forceinline__ s4 pack4(const float* v) {
       s4, u32x2f{__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi)});
 }
 
-template <int N>
+template <int N, int W>
 __device__ __forceinline__ void tile_bf16(const Lvl3& L, const float* __restrict__ qo,
                                           float* __restrict__ qn, float* __restrict__ res,
                                           const double* __restrict__ qb3, float A, float B,
@@ -817,7 +825,7 @@ __device__ __forceinline__ void tile_bf16(const Lvl3& L, const float* __restrict
   constexpr unsigned FS = Np * kTile * 4;   // bytes between two fields of a tile
   constexpr unsigned TS = 4 * FS;           // bytes per tile
   const int shot = (int)(item / ngrp);
-  const int tile = (int)(item - (long long)shot * ngrp) * kWaves3f + (threadIdx.x >> 6);
+  const int tile = (int)(item - (long long)shot * ngrp) * W + (threadIdx.x >> 6);
   if (tile >= L.ntile) return;
   qo += shot * sh.st3;
   qn += shot * sh.st3;
@@ -1003,8 +1011,8 @@ __device__ __forceinline__ void tile_bf16(const Lvl3& L, const float* __restrict
   }
 }
 
-template <int N>
-__global__ void __launch_bounds__(kWaves3f * 64, Dims3b<N>::kOcc) k_level3_bf16(
+template <int N, int W>
+__global__ void __launch_bounds__(W * 64, W == 8 ? 1 : Dims3b<N>::kOcc) k_level3_bf16(
     Lvl3 L, const float* __restrict__ qo, float* __restrict__ qn, float* __restrict__ res,
     const double* __restrict__ qb3, float A, float B, float dt, Shots sh) {
   using D = Dims3b<N>;
@@ -1014,17 +1022,17 @@ __global__ void __launch_bounds__(kWaves3f * 64, Dims3b<N>::kOcc) k_level3_bf16(
   int* smap = smask + 4 * Nfp;
   // fragments after the maps, at an 8-byte boundary
   s4* sops = reinterpret_cast<s4*>(sfl + ((4 * Nfp + 96 * Nfp + 1) & ~1));
-  fill_lds<kWaves3f * 64, 4 * Nfp>(smask, L.fmask, threadIdx.x);
-  fill_lds<kWaves3f * 64, 96 * Nfp>(smap, L.fmap, threadIdx.x);
-  fill_lds<kWaves3f * 64, D::NFR * 64>(reinterpret_cast<unsigned long long*>(sops),
+  fill_lds<W * 64, 4 * Nfp>(smask, L.fmask, threadIdx.x);
+  fill_lds<W * 64, 96 * Nfp>(smap, L.fmap, threadIdx.x);
+  fill_lds<W * 64, D::NFR * 64>(reinterpret_cast<unsigned long long*>(sops),
                                        reinterpret_cast<const unsigned long long*>(L.opsb),
                                        threadIdx.x);
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int ngrp = (L.ntile + kWaves3f - 1) / kWaves3f;
+  const int ngrp = (L.ntile + W - 1) / W;
   const XcdRange rg_(ngrp * (long long)sh.n, L.order);
   for (long long item = rg_.lo; item < rg_.hi; item += rg_.step)
-    tile_bf16<N>(L, qo, qn, res, qb3, A, B, dt, sh, item, ngrp, smap, smask, sops, lane);
+    tile_bf16<N, W>(L, qo, qn, res, qb3, A, B, dt, sh, item, ngrp, smap, smask, sops, lane);
 }
 
 // ------------------------------------------ BF16 contractions, tile on chip ---
@@ -1385,28 +1393,34 @@ hipError_t launch3b_dma(const Lvl3& L, const float* qo, float* qn, float* res, c
   return hipGetLastError();
 }
 
+template <int N, int W>
+hipError_t launch3b_reg(const Lvl3& L, const float* qo, float* qn, float* res, const double* qb3,
+                        double A, double B, double dt, const Shots& sh, hipStream_t st) {
+  using D = Dims3b<N>;
+  constexpr int Nfp = D::Nfp;
+  const size_t lds = sizeof(float) * ((4 * Nfp + 96 * Nfp + 1) & ~1) + (size_t)D::NFR * 512;
+  const int ngrp = (L.ntile + W - 1) / W;
+  if (sh.n < 1) return hipErrorInvalidValue;
+  int resident = 0;
+  {
+    const hipError_t e = kernel_setup((const void*)(k_level3_bf16<N, W>), W * 64, lds, &resident);
+    if (e != hipSuccess) return e;
+  }
+  const long long items = (long long)ngrp * sh.n;
+  const int blocks = grid3(resident, items, L.eighths);
+  hipLaunchKernelGGL((k_level3_bf16<N, W>), dim3(blocks), dim3(W * 64), lds, st, L, qo, qn, res,
+                     qb3, (float)A, (float)B, (float)dt, sh);
+  return hipGetLastError();
+}
+
 template <int N>
 hipError_t launch3b(const Lvl3& L, const float* qo, float* qn, float* res, const double* qb3,
                     double A, double B, double dt, const Shots& sh, hipStream_t st) {
   if constexpr (N <= 5) {   // the tile buffers and fragments fit the LDS up to N = 5
     if (L.kvar == 0) return launch3b_dma<N>(L, qo, qn, res, qb3, A, B, dt, sh, st);
   }
-  using D = Dims3b<N>;
-  constexpr int Nfp = D::Nfp;
-  const size_t lds = sizeof(float) * ((4 * Nfp + 96 * Nfp + 1) & ~1) + (size_t)D::NFR * 512;
-  const int ngrp = (L.ntile + kWaves3f - 1) / kWaves3f;
-  if (sh.n < 1) return hipErrorInvalidValue;
-  int resident = 0;
-  {
-    const hipError_t e =
-        kernel_setup((const void*)(k_level3_bf16<N>), kWaves3f * 64, lds, &resident);
-    if (e != hipSuccess) return e;
-  }
-  const long long items = (long long)ngrp * sh.n;
-  const int blocks = grid3(resident, items, L.eighths);
-  hipLaunchKernelGGL(k_level3_bf16<N>, dim3(blocks), dim3(kWaves3f * 64), lds, st, L, qo, qn, res,
-                     qb3, (float)A, (float)B, (float)dt, sh);
-  return hipGetLastError();
+  if (L.waves == 8) return launch3b_reg<N, 8>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+  return launch3b_reg<N, 4>(L, qo, qn, res, qb3, A, B, dt, sh, st);
 }
 
 }  // namespace

@@ -33,12 +33,6 @@ namespace {
 //   B (fields at nodes 4ks + k of the 16 elements):  lane l -> B[l/16][l%16]
 //   D (rows 4rg + k, elements):                       lane l -> D[l/16][l%16]
 // so each instruction accumulates one double per lane.
-// waves (tiles) per workgroup of the register-streaming 3D kernel: four
-// (one wave per SIMD) except at N = 5, where the operators fill the LDS and
-// eight waves share them (two per SIMD at 256 registers each: the second
-// wave covers the first one's waits on memory; 1,233 -> 910 us per launch
-// at 40^3, although the compiler then spills 36 registers)
-constexpr int kWaves3 = 4;
 
 template <int N>
 struct Dims3 {
@@ -50,8 +44,16 @@ struct Dims3 {
   // operator fragments in LDS up to 150 KB (N <= 6); above 64 KB the kernel
   // runs one workgroup per CU, with 512 registers per wave
   static constexpr bool kLds = NFRAG * 16 * 8 <= 150 * 1024;
-  static constexpr int kOcc = NFRAG * 16 * 8 <= 64 * 1024 ? 2 : 1;
-  static constexpr int kWaves = N == 5 ? 8 : kWaves3;
+};
+
+// waves (tiles) per workgroup of the register-streaming 3D kernel: W = 4
+// or 8 (Lvl3::waves; a tuning axis).  With the operators in LDS at N = 5
+// eight waves share them, two per SIMD at 256 registers each: the second
+// wave covers the first one's waits on memory (1,233 -> 910 us per launch
+// at 40^3, although the compiler then spills 36 registers).
+template <int N, int W>
+struct Occ3 {   // workgroups per CU the registers are sized for
+  static constexpr int value = W == 8 ? 1 : (Dims3<N>::NFRAG * 16 * 8 <= 64 * 1024 ? 2 : 1);
 };
 
 // Buffer-resource access: a 32-bit per-lane byte offset plus a uniform
@@ -77,7 +79,7 @@ __device__ __forceinline__ void bstn(Rsrc r, unsigned voff, unsigned soff, doubl
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 2);
 }
 
-template <int N>
+template <int N, int W>
 __device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restrict__ qo,
                                           double* __restrict__ qn, double* __restrict__ res,
                                           const double* __restrict__ qb3, double A, double B,
@@ -85,8 +87,8 @@ __device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restric
                                           const int* smap, const int* smask, const double* sops,
                                           int lane);
 
-template <int N>
-__global__ void __launch_bounds__(Dims3<N>::kWaves * 64, Dims3<N>::kOcc) k_level3(Lvl3 L, const double* __restrict__ qo,
+template <int N, int W>
+__global__ void __launch_bounds__(W * 64, (Occ3<N, W>::value)) k_level3(Lvl3 L, const double* __restrict__ qo,
                                                    double* __restrict__ qn, double* __restrict__ res,
                                                    const double* __restrict__ qb3, double A, double B,
                                                    double dt, Shots sh) {
@@ -99,23 +101,23 @@ __global__ void __launch_bounds__(Dims3<N>::kWaves * 64, Dims3<N>::kOcc) k_level
   int* smask = reinterpret_cast<int*>(sfrag);
   int* smap = smask + 4 * Nfp;
   constexpr int kTabDoubles = (4 * Nfp + 96 * Nfp + 1) / 2;
-  fill_lds<D::kWaves * 64, 4 * Nfp>(smask, L.fmask, threadIdx.x);
-  fill_lds<D::kWaves * 64, 96 * Nfp>(smap, L.fmap, threadIdx.x);
+  fill_lds<W * 64, 4 * Nfp>(smask, L.fmask, threadIdx.x);
+  fill_lds<W * 64, 96 * Nfp>(smap, L.fmap, threadIdx.x);
   double* sops = sfrag + kTabDoubles;
-  if (D::kLds) fill_lds<D::kWaves * 64, D::NFRAG * 16>(sops, L.ops, threadIdx.x);
+  if (D::kLds) fill_lds<W * 64, D::NFRAG * 16>(sops, L.ops, threadIdx.x);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   // persistent: the workgroup loads its tables once, then its waves take
-  // (shot, group of kWaves tiles) items from its XCD's range
-  const int ngrp = (L.ntile + D::kWaves - 1) / D::kWaves;
+  // (shot, group of W tiles) items from its XCD's range
+  const int ngrp = (L.ntile + W - 1) / W;
   const XcdRange rg_(ngrp * (long long)sh.n, L.order);
   for (long long item = rg_.lo; item < rg_.hi; item += rg_.step)
-    tile_step<N>(L, qo, qn, res, qb3, A, B, dt, sh, item, ngrp, smap, smask, sops, lane);
+    tile_step<N, W>(L, qo, qn, res, qb3, A, B, dt, sh, item, ngrp, smap, smask, sops, lane);
 }
 
-// One wave's share of one work item: tile (item mod ngrp) kWaves + wave of
+// One wave's share of one work item: tile (item mod ngrp) W + wave of
 // shot item / ngrp.
-template <int N>
+template <int N, int W>
 __device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restrict__ qo,
                                           double* __restrict__ qn, double* __restrict__ res,
                                           const double* __restrict__ qb3, double A, double B,
@@ -127,7 +129,7 @@ __device__ __forceinline__ void tile_step(const Lvl3& L, const double* __restric
   constexpr unsigned FS = Np * kTile * 8;   // bytes between two fields of a tile
   constexpr unsigned TS = 4 * FS;           // bytes per tile
   const int shot = (int)(item / ngrp);
-  const int tile = (int)(item - (long long)shot * ngrp) * D::kWaves + (threadIdx.x >> 6);
+  const int tile = (int)(item - (long long)shot * ngrp) * W + (threadIdx.x >> 6);
   if (tile >= L.ntile) return;
   qo += shot * sh.st3;
   qn += shot * sh.st3;
@@ -866,27 +868,35 @@ hipError_t launch3_group(const Member3* G, int nm, long long total, double A, do
   return hipGetLastError();
 }
 
-template <int N>
-hipError_t launch3_reg(const Lvl3& L, const double* qo, double* qn, double* res,
-                       const double* qb3, double A, double B, double dt, const Shots& sh,
-                       hipStream_t st) {
+template <int N, int W>
+hipError_t launch3_reg_w(const Lvl3& L, const double* qo, double* qn, double* res,
+                         const double* qb3, double A, double B, double dt, const Shots& sh,
+                         hipStream_t st) {
   using D = Dims3<N>;
   constexpr int Nfp = D::Nfp;
   const size_t lds = sizeof(double) * ((4 * Nfp + 96 * Nfp + 1) / 2 + (D::kLds ? D::NFRAG * 16 : 0));
-  const int ngrp = (L.ntile + D::kWaves - 1) / D::kWaves;
+  const int ngrp = (L.ntile + W - 1) / W;
   if (sh.n < 1) return hipErrorInvalidValue;
   // persistent grid: as many workgroups as fit on the device at once
   int resident = 0;
   {
-    const hipError_t e = kernel_setup((const void*)(k_level3<N>), D::kWaves * 64, lds, &resident);
+    const hipError_t e = kernel_setup((const void*)(k_level3<N, W>), W * 64, lds, &resident);
     if (e != hipSuccess) return e;
   }
   const long long items = (long long)ngrp * sh.n;
   // a multiple of 8, so that every XCD has blocks for its range of items
   const int blocks = grid3(resident, items, L.eighths);
-  hipLaunchKernelGGL(k_level3<N>, dim3(blocks), dim3(D::kWaves * 64), lds, st, L, qo, qn, res,
-                     qb3, A, B, dt, sh);
+  hipLaunchKernelGGL((k_level3<N, W>), dim3(blocks), dim3(W * 64), lds, st, L, qo, qn, res, qb3,
+                     A, B, dt, sh);
   return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch3_reg(const Lvl3& L, const double* qo, double* qn, double* res,
+                       const double* qb3, double A, double B, double dt, const Shots& sh,
+                       hipStream_t st) {
+  if (L.waves == 8) return launch3_reg_w<N, 8>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+  return launch3_reg_w<N, 4>(L, qo, qn, res, qb3, A, B, dt, sh, st);
 }
 
 // N <= 4: the tile-on-chip kernel (its registers and LDS hold a whole

@@ -452,10 +452,11 @@ def test_graph_replay_equals_eager(precision):
     print(f"[graph] precision {precision}: replayed == eager bitwise", flush=True)
 
 
-@pytest.mark.parametrize("precision,N", [(0, 4), (2, 4), (3, 4), (2, 5), (3, 5), (3, 6)])
+@pytest.mark.parametrize("precision,N", [(0, 4), (0, 5), (2, 4), (3, 4), (2, 5), (3, 5), (3, 6)])
 def test_tuning_candidates_and_autotune(precision, N):
     """Every launch candidate of the 3D level (tile on chip / register
-    streaming x XCD ranges / round robin) matches the oracle on a layered
+    streaming with 4 or 8 waves per workgroup x XCD ranges / round robin x
+    three persistent grid sizes) matches the oracle on a layered
     medium with a source (FP64 to round-off, the FP32 variant to its error
     level); autotune leaves the state as it was and picks one of them."""
     n, P, steps, dt = 5, 3, 6, 1e-3
@@ -466,7 +467,7 @@ def test_tuning_candidates_and_autotune(precision, N):
     ref = run_oracle(case, steps, dt)
     s = make_solver(case, precision=precision)
     count = s.tuning_count()
-    assert count == (12 if N <= (4 if precision == 0 else 5) else 6)
+    assert count == (18 if N <= (4 if precision == 0 else 5) else 12)
     for cand in range(count):
         s.set_state(case["state"])
         s.set_tuning(cand)
