@@ -112,7 +112,7 @@ def build_batch_workload(n=20, N=4, P=3, shots=64):
 def run_uneven(args):
     """Uneven batch: meshes of 10^3, 16^3 and 24^3 cells (x 6 tets), N = 4,
     HABC P = 3, rho = c = 1, one Ricker source each at a seeded interior
-    position, FP64 or the FP32 variant (--precision); stepped as one group
+    position, FP64 or the FP32 or BF16 variant (--precision); stepped as one group
     (one 3D launch per stage over all their tiles) and, for comparison, one
     after the other."""
     import numpy as np
@@ -121,9 +121,8 @@ def run_uneven(args):
     from paper_1610_05023_amd import Solver
     from paper_1610_05023_amd.binding import step_group
     N, P, sizes = 4, 3, (10, 16, 24)
-    if args.precision == "bf16":
-        sys.exit("bench.py: the uneven group runs FP64 or FP32 (the BF16 variant has no group kernel)")
-    prec = 2 if args.precision == "fp32" else 0
+    prec = {"fp64": 0, "fp32": 2, "bf16": 3}[args.precision]
+    name = {0: "FP64", 2: "FP32", 3: "BF16-contraction"}[prec]
     solvers, U = [], 0
     xs = w.shot_positions(len(sizes), seed=6)
     for j, n in enumerate(sizes):
@@ -153,8 +152,8 @@ def run_uneven(args):
         "metric": METRIC, "value": U * 5 * args.steps / el, "unit": "DOF-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if prec else "f64", "data": "synthetic",
-        "config": {"workload": f"uneven group: {'FP32' if prec else 'FP64'} DG+HABC steps of "
+        "vs_baseline": None, "dtype": {0: "f64", 2: "f32", 3: "bf16"}[prec], "data": "synthetic",
+        "config": {"workload": f"uneven group: {name} DG+HABC steps of "
                                "three Kuhn meshes of "
                                "10^3, 16^3 and 24^3 cells x 6 tets stepped together, N=4, HABC "
                                "P=3, rho=c=1, one Ricker source each (seed 6)",
@@ -168,8 +167,8 @@ def run_uneven(args):
 
 def run_reflection(args):
     """Accuracy of the absorbing boundary at full size.  The 40^3 x 6-tet
-    layered case with its Ricker source is run with HABC P = 6 and with the
-    basic ABC (P = 0).  The reference is the doubled domain [-0.5, 1.5]^3
+    layered case with its Ricker source is run with HABC P = 6 and P = 3 and
+    with the basic ABC (P = 0).  The reference is the doubled domain [-0.5, 1.5]^3
     (80^3 x 6 tets, the same cell size, layers extended sideways and the
     bottom and top layers downwards and upwards, HABC P = 6).  All three are
     stepped to t = 0.45.  The waves reach the unit cube's faces from
@@ -226,7 +225,7 @@ def run_reflection(args):
 
     VX, E = w.kuhn_mesh(n)
     rho, c = medium(n, 0)
-    inner = {f"P={P}": run(VX, E, rho, c, P, f"P={P}") for P in (6, 0)}
+    inner = {f"P={P}": run(VX, E, rho, c, P, f"P={P}") for P in (6, 3, 0)}
     if args.closure:
         from paper_1610_05023_amd.closure import teacher_samples, train
         t0 = time.perf_counter()

@@ -164,9 +164,9 @@ dgh_status dgh_step(dgh_ctx* ctx, int n_steps, double dt, double t_start);
  * of any size, with their own shots, materials and sources -- by n_steps
  * steps together; each stage runs the 3D level of all of them in one
  * persistent launch over a work list of their tiles, then the face, edge
- * and corner levels of each.  The members need the same precision (FP64 or
- * the FP32 variant), the same N <= 4, the tile-on-chip kernel (tuning
- * candidate 0 or 1), the same device and stream, and no closure; results
+ * and corner levels of each.  The members need the same precision (FP64,
+ * FP32 or BF16 contractions), the same N <= 4, the tile-on-chip kernel (tuning
+ * candidates 0-5), the same device and stream, and no closure; results
  * equal stepping each alone.  The member tables
  * live in ctxs[0]'s workspace.  Synchronises the stream once at the start.
  * DGH_EINVAL on a mismatch (reason in ctxs[0]'s dgh_last_error). */

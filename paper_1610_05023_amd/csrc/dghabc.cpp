@@ -1234,10 +1234,9 @@ dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, d
     if (c->stage < S_BOUND) return fail(c0, DGH_ESTATE, "group member not bound");
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return fail(c0, DGH_EINVAL, "a context appears twice in the group");
-    if (c->N > 4 || c->L3.kvar != 0 || c->precision == DGH_BF16_MFMA)
-      return fail(c0, DGH_EINVAL,
-                  "group steps need N <= 4, FP64 or FP32 and the tile-on-chip kernel");
-    if (c->N != c0->N || c->lay.e3 != c0->lay.e3 || c->device != c0->device ||
+    if (c->N > 4 || c->L3.kvar != 0)
+      return fail(c0, DGH_EINVAL, "group steps need N <= 4 and the tile-on-chip kernel");
+    if (c->N != c0->N || c->precision != c0->precision || c->device != c0->device ||
         c->stream != c0->stream)
       return fail(c0, DGH_EINVAL, "group members need the same N, precision, device and stream");
     if (c->closure || c->record) return fail(c0, DGH_EINVAL, "group steps run the plain method");
@@ -1281,7 +1280,10 @@ dgh_status dgh_step_group(dgh_ctx* const* ctxs, int n, int n_steps, double dt, d
     const double t = t_start + it * dt;
     for (int s = 0; s < 5; ++s) {
       const int par = (it * 5 + s) & 1;
-      if (c0->lay.e3 == 4)
+      if (c0->precision == DGH_BF16_MFMA)
+        HIPCHECK(c0, dgh::launch_level3_bf16_group(dev + par * n, n, total, c0->N, kA[s], kB[s],
+                                                   dt, t + kC[s] * dt, kC[s], st));
+      else if (c0->lay.e3 == 4)
         HIPCHECK(c0, dgh::launch_level3_f32_group(dev + par * n, n, total, c0->N, kA[s], kB[s],
                                                   dt, t + kC[s] * dt, kC[s], st));
       else

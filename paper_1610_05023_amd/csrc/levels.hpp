@@ -163,6 +163,8 @@ hipError_t launch_level3_group(const Member3* G, int nm, long long total, int N,
                                double B, double dt, double tau, double cs, hipStream_t st);
 hipError_t launch_level3_f32_group(const Member3* G, int nm, long long total, int N, double A,
                                    double B, double dt, double tau, double cs, hipStream_t st);
+hipError_t launch_level3_bf16_group(const Member3* G, int nm, long long total, int N, double A,
+                                   double B, double dt, double tau, double cs, hipStream_t st);
 
 // the device clock of replayed stepping: clk = {t0, 0}; clk[1] += 1
 hipError_t launch_clock_set(double* clk, double t0, hipStream_t st);

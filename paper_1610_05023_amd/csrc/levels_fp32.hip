@@ -1374,6 +1374,80 @@ __global__ void __launch_bounds__(kWavesF * 64, 1) k_level3_bf16_dma(
   }
 }
 
+// The same kernel over a group of contexts (any mesh sizes, same N), as
+// the FP32 group kernel: one work list, member c owning
+// [first_c, first_c + items_c).
+template <int N>
+__global__ void __launch_bounds__(kWavesF * 64, 1) k_level3_bf16_dma_group(
+    const Member3* __restrict__ G, int nm, long long total, float A, float B, float dt,
+    double tau, double cs) {
+  using D = Dims3b<N>;
+  using LB = LdsB<N>;
+  constexpr int Nfp = D::Nfp;
+  extern __shared__ float sfl[];
+  int* smask = reinterpret_cast<int*>(sfl);
+  int* smap = smask + 4 * Nfp;
+  s4* sops = reinterpret_cast<s4*>(reinterpret_cast<char*>(sfl) + LB::TAB);
+  const int lane = threadIdx.x & 63;
+  const XcdRange rg_(total, G[0].L.order);
+  char* buf = reinterpret_cast<char*>(sfl) + LB::BUF +
+              __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * BufF<N>::BYTES;
+  auto member = [&](long long it) {
+    int c = 0;
+    while (c + 1 < nm && G[c + 1].first <= it) ++c;
+    return c;
+  };
+  auto shots = [&](int c) {
+    Shots sh = G[c].sh;
+    sh.tau = tau;
+    sh.cs = cs;
+    sh.clk = nullptr;
+    return sh;
+  };
+  if (rg_.lo < rg_.hi) {
+    const int c = member(rg_.lo);
+    tile_dma_f<N>(G[c].L, static_cast<const float*>(G[c].qo), shots(c), rg_.lo - G[c].first,
+                  G[c].ngrp, buf, lane);
+  }
+  fill_lds<kWavesF * 64, 4 * Nfp>(smask, G[0].L.fmask, threadIdx.x);
+  fill_lds<kWavesF * 64, 96 * Nfp>(smap, G[0].L.fmap, threadIdx.x);
+  fill_lds<kWavesF * 64, D::NFR * 64>(reinterpret_cast<unsigned long long*>(sops),
+                                      reinterpret_cast<const unsigned long long*>(G[0].L.opsb),
+                                      threadIdx.x);
+  __syncthreads();
+  for (long long it = rg_.lo; it < rg_.hi; it += rg_.step) {
+    const long long nx = it + rg_.step;
+    const int c = member(it);
+    const Shots sh = shots(c);
+    auto fetch = [&]() {
+      if (nx < rg_.hi) {
+        const int cn = member(nx);
+        tile_dma_f<N>(G[cn].L, static_cast<const float*>(G[cn].qo), shots(cn),
+                      nx - G[cn].first, G[cn].ngrp, buf, lane);
+      }
+    };
+    tile_bf16_dma<N>(G[c].L, static_cast<const float*>(G[c].qo), static_cast<float*>(G[c].qn),
+                     static_cast<float*>(G[c].res), G[c].qb3, A, B, dt, sh, it - G[c].first,
+                     fetch, G[c].ngrp, smap, smask, sops, buf, lane);
+  }
+}
+
+template <int N>
+hipError_t launch3b_group(const Member3* G, int nm, long long total, double A, double B,
+                          double dt, double tau, double cs, hipStream_t st) {
+  const size_t lds = LdsB<N>::BYTES;
+  int resident = 0;
+  {
+    const hipError_t e =
+        kernel_setup((const void*)(k_level3_bf16_dma_group<N>), kWavesF * 64, lds, &resident);
+    if (e != hipSuccess) return e;
+  }
+  const int blocks = (int)std::max<long long>(8, std::min<long long>(resident, total) / 8 * 8);
+  hipLaunchKernelGGL(k_level3_bf16_dma_group<N>, dim3(blocks), dim3(kWavesF * 64), lds, st, G,
+                     nm, total, (float)A, (float)B, (float)dt, tau, cs);
+  return hipGetLastError();
+}
+
 template <int N>
 hipError_t launch3b_dma(const Lvl3& L, const float* qo, float* qn, float* res, const double* qb3,
                         double A, double B, double dt, const Shots& sh, hipStream_t st) {
@@ -1446,6 +1520,17 @@ hipError_t launch_level3_f32(const Lvl3& L, const float* qo, float* qn, float* r
     case 4: return launch3f<4>(L, qo, qn, res, qb3, A, B, dt, sh, st);
     case 5: return launch3f<5>(L, qo, qn, res, qb3, A, B, dt, sh, st);
     case 6: return launch3f<6>(L, qo, qn, res, qb3, A, B, dt, sh, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_level3_bf16_group(const Member3* G, int nm, long long total, int N, double A,
+                                    double B, double dt, double tau, double cs, hipStream_t st) {
+  switch (N) {
+    case 1: return launch3b_group<1>(G, nm, total, A, B, dt, tau, cs, st);
+    case 2: return launch3b_group<2>(G, nm, total, A, B, dt, tau, cs, st);
+    case 3: return launch3b_group<3>(G, nm, total, A, B, dt, tau, cs, st);
+    case 4: return launch3b_group<4>(G, nm, total, A, B, dt, tau, cs, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -353,6 +353,38 @@ def test_batched_shots_match_single_runs():
         assert max(err.values()) <= TOL, (k, err)
 
 
+@pytest.mark.parametrize("precision,N", [(0, 4), (2, 4), (3, 4), (3, 5), (2, 6)])
+def test_batched_shots_equal_single_shot_runs(precision, N):
+    """Three shots stepped together equal, bit for bit, three contexts of
+    one shot each with the same states and sources: the shot index changes
+    where a work item reads and writes, not its arithmetic.  Every 3D kernel
+    kind (FP64 and FP32 / BF16 tile on chip, FP32 register streaming at
+    N = 6), the face, edge and corner levels."""
+    from paper_1610_05023_amd import Solver
+    n, P, steps, dt = 5, 3, 8, 1e-3
+    base = make_case(n=n, N=N, P=P, medium="layered", init="zero")
+    kw = dict(face_bc=base["face_bc"], periodic=base["periodic"], box=base["box"],
+              precision=precision)
+    cases = [make_case(n=n, N=N, P=P, medium="layered", init="random", seed=140 + 9 * k,
+                       source=(xs, 6.0 + k, 0.02 + 0.01 * k))
+             for k, xs in enumerate([(0.41, 0.52, 0.33), (0.71, 0.3, 0.61), (0.22, 0.81, 0.47)])]
+    s = Solver(base["VX"], base["E"], N, P, base["rho"], base["c"], n_shots=3, **kw).bind()
+    for k, c in enumerate(cases):
+        s.set_state(c["state"], shot=k)
+        s.set_source(*c["source"], shot=k)
+    s.step(steps, dt)
+    for k, c in enumerate(cases):
+        one = Solver(base["VX"], base["E"], N, P, base["rho"], base["c"], **kw).bind()
+        one.set_state(c["state"])
+        one.set_source(*c["source"])
+        one.step(steps, dt)
+        a, b = s.read_fields(shot=k), one.read_fields()
+        one.close()
+        for name in a:
+            assert np.array_equal(a[name], b[name]), (k, name)
+    s.close()
+
+
 @pytest.mark.parametrize("N,P", [(1, 1), (2, 0), (3, 12), (5, 2), (6, 1)])
 def test_degrees_and_habc_orders(N, P):
     """Every compiled degree and HABC orders 0 (face rule only), 1, 2, 12
@@ -546,11 +578,11 @@ def test_state_and_source_writes_wait_for_a_side_stream():
         assert np.array_equal(want[k], got[k]), k
 
 
-@pytest.mark.parametrize("precision", [0, 2])
+@pytest.mark.parametrize("precision", [0, 2, 3])
 def test_group_step_equals_separate_runs(precision):
     """An uneven group (meshes of 3^3, 4^3 and 5^3 cells, one of them with
     two shots, the largest in a layered medium, each shot with its own
-    source and random state), FP64 or the FP32 variant,
+    source and random state), FP64 or the FP32 or BF16 variant,
     stepped together -- one 3D launch per stage over all their tiles --
     equals each context stepped alone, bitwise; a member with another N or
     another precision is refused."""
@@ -593,9 +625,7 @@ def test_group_step_equals_separate_runs(precision):
     with pytest.raises(DghError):
         step_group([group[0], s3], 1, dt)
     same_n = make_case(n=3, N=N, P=P, init="zero")
-    s4 = make_solver(same_n, precision=2 - precision)
-    with pytest.raises(DghError):
-        step_group([group[0], s4], 1, dt)
-    s5 = make_solver(same_n, precision=3)        # the BF16 variant has no group kernel
-    with pytest.raises(DghError):
-        step_group([s5], 1, dt)
+    for other_precision in {0, 2, 3} - {precision}:
+        s4 = make_solver(same_n, precision=other_precision)
+        with pytest.raises(DghError):
+            step_group([group[0], s4], 1, dt)
