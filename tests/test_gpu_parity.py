@@ -404,6 +404,35 @@ def test_full_size_layered_one_step():
     _check(case, 1, w.kuhn_dt(n, 4, 3.0), t0=0.01)
 
 
+@pytest.mark.parametrize("precision", [2, 3])
+def test_full_size_mixed_precision_one_step(precision):
+    """The N = 5 throughput workload at full size (40^3 x 6 tets, HABC P = 3,
+    layered medium, Ricker source) in the bench's launch configuration of
+    the FP32 or BF16 variant (the tile-on-chip kernel): one step from a
+    random state of every array against the FP64 library on the same state
+    (itself held to the oracle by the tests above, and at N = 5 on the
+    largest mesh).  One step changes q by dt times the right-hand side, so
+    the state arrays keep the input's FP32 rounding plus that part's error:
+    FP32 within 1e-5 (residuals 1e-3), BF16 within 1e-2 (residuals 0.1)."""
+    n = 40
+    case = make_case(n=n, N=5, P=3, medium="layered", init="random", seed=321,
+                     source=((0.5 + 0.3 / n, 0.5 + 0.2 / n, 0.5 + 0.1 / n), 80.0, 0.0125))
+    dt = w.kuhn_dt(n, 5, 3.0)
+    ref = make_solver(case)
+    ref.step(1, dt, 0.01)
+    want = ref.read_fields()
+    ref.close()
+    s = make_solver(case, precision=precision)
+    s.step(1, dt, 0.01)
+    err = rel_errors(s.read_fields(), want)
+    s.close()
+    tol, tol_res = {2: (1e-5, 1e-3), 3: (1e-2, 0.1)}[precision]
+    print(f"[full size mixed] precision {precision}",
+          {k: f"{v:.1e}" for k, v in err.items()}, flush=True)
+    for k, v in err.items():
+        assert v <= (tol_res if k.startswith("res") else tol), (k, v)
+
+
 # FP32: every field, at 10, 200 and 1000 steps; BF16: the 3D fields (the
 # other levels and the residuals hold values far below the pulse's size
 # early on, where relative errors say little: reported, not guarded)
