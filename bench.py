@@ -79,6 +79,16 @@ def profiled_traffic():
     return float(fields["traffic_bytes_per_launch_k_level3"])
 
 
+def kernel_name(prec, N, tuned):
+    """The 3D kernel a launch runs: the tile-on-chip kernel where the tile
+    fits (FP64 N <= 4, FP32 and BF16 N <= 5) unless tuning chose register
+    streaming (launch candidates 6 and above there)."""
+    base = {0: "k_level3", 2: "k_level3_f32", 3: "k_level3_bf16"}[prec]
+    on_chip = N <= (4 if prec == 0 else 5)
+    cand = tuned.get("candidate", 0) if isinstance(tuned, dict) else 0
+    return base + "_dma" if on_chip and cand < 6 else base
+
+
 def achieved_gbs(alg_bytes, avg_ms):
     return alg_bytes / (avg_ms * 1e-3) / 1e9
 
@@ -608,14 +618,13 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
-                     "kernel": ({0: "k_level3_dma" if wl["N"] <= 4 else "k_level3",
-                                 2: "k_level3_f32_dma" if wl["N"] <= 4 else "k_level3_f32",
-                                 3: "k_level3_bf16"}[prec] +
-                                " (3D volume + surface + LSRK update)"),
+                     "kernel": kernel_name(prec, wl["N"], tuned) +
+                               " (3D volume + surface + LSRK update)",
                      "avg_us": avg3_ms * 1e3, "alg_bytes_per_launch": alg,
                      "step_achieved": step_gbs, "step_frac": step_gbs / HBM_PEAK_GBS,
                      "measured_copy_gbs": copy_gbs,
                      "frac_of_measured_copy": achieved / copy_gbs,
+                     "step_frac_of_measured_copy": step_gbs / copy_gbs,
                      "step_alg_bytes": step_alg,
                      "step_note": "all levels' algorithmic bytes per step / ms_per_step"},
         "cpu_baseline": cpu,
