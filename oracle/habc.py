@@ -1,5 +1,5 @@
 """Pade-type HABC coefficients and the edge/corner compatibility equations
-(oracle, FP64).
+(oracle, FP64; test infrastructure, never imported by the library).
 
 Section 2.1: f_P(X) approximates sqrt(1+X) with M = 2P+1 and coefficients
 gamma_n = tan^2(n pi / M) (the paper's c_n), in the two equivalent forms of

@@ -1,4 +1,5 @@
-"""Affine geometry and four-level connectivity of the oracle (FP64).
+"""Affine geometry and four-level connectivity of the oracle (FP64; test
+infrastructure, never imported by the library).
 
 Section 3.2: the volume mesh of K_tet tetrahedra; the surface mesh of the
 tetrahedron faces lying on HABC faces of the cuboid (K_tri triangles); the

@@ -1,4 +1,5 @@
-"""Nodal reference elements of the oracle (FP64).
+"""Nodal reference elements of the oracle (FP64; test infrastructure, never
+imported by the library).
 
 Section 3.2 of the paper: nodal DG on tetrahedra, triangles and lines; the
 tetrahedron nodes come from the Warp & Blend construction (Warburton 2006)

@@ -1,4 +1,5 @@
-"""The multidimensional explicit step of the oracle (FP64).
+"""The multidimensional explicit step of the oracle (FP64; test
+infrastructure, never imported by the library).
 
 Algorithm 1 of the paper, discretised as in Section 3.2: nodal DG with
 upwind fluxes on the volume (3D), the HABC faces (2D, P sets of fields per
