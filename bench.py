@@ -190,7 +190,7 @@ def run_reflection(args):
     the network's history of step ends spans the same time as in use.
     --teacher small uses the test's small recipe (six pulses on 8^3 x 6
     tets, c = 1); --teacher case uses four pulses on this case's own mesh
-    and medium, centred away from the source; --teacher config1 uses 200
+    and medium, centred away from the source; --teacher parity uses 200
     runs of the 8^3 x 6-tet parity case (N = 3, HABC P = 3, rho = c = 1,
     Gaussian pulse of width 0.05) at seeded random centres, each at that
     case's own time step to t = 1, and trains with the BF16 gradient
@@ -242,7 +242,7 @@ def run_reflection(args):
         print(f"[bench] reflection: training the closure ({args.teacher} teacher runs)",
               file=sys.stderr, flush=True)
         train_kw = dict(iters=2500, batch=4096, lr=1e-3, seed=5)
-        if args.teacher == "config1":
+        if args.teacher == "parity":
             c1 = w.config("1")
             VXt, Et = w.kuhn_mesh(c1.n)
             Kt = Et.shape[0]
@@ -432,7 +432,7 @@ def main():
                     help="P = 0 with the learned boundary closure (layered workload: seeded "
                          "random weights, the cost does not depend on them; reflection "
                          "workload: trained first, then evaluated)")
-    ap.add_argument("--teacher", choices=["small", "case", "config1"], default="small",
+    ap.add_argument("--teacher", choices=["small", "case", "parity"], default="small",
                     help="reflection --closure: teacher runs of the small recipe (8^3, c = 1), "
                          "on the case's own mesh and medium, or 200 runs of the 8^3 parity "
                          "case (BF16 training)")

@@ -385,6 +385,22 @@ def test_batched_shots_equal_single_shot_runs(precision, N):
     s.close()
 
 
+@pytest.mark.parametrize("n,N,P,precision", [(1, 1, 1, 0), (1, 3, 3, 0), (1, 4, 6, 0),
+                                              (1, 5, 2, 0), (2, 2, 2, 0), (1, 4, 3, 2),
+                                              (1, 4, 3, 3), (2, 5, 3, 3)])
+def test_one_and_two_cell_meshes(n, N, P, precision):
+    """Degenerate meshes: one hex cell per side (6 tetrahedra, one ragged
+    tile of 16 slots, every element on three HABC faces, each of the 12
+    lines with both ends at corners, each corner's three lines in one
+    launch) and two cells per side; every array random, rho = c = 1, 20
+    steps against the oracle.  FP64 to round-off, the FP32
+    variant to 1e-4, the BF16 contractions to 1e-2 (residuals 0.3)."""
+    case = make_case(n=n, N=N, P=P, init="random", seed=200 + 10 * n + N + P)
+    _check(case, 20, 0.5 * w.kuhn_dt(n, N, 1.0),
+           tol={0: TOL, 2: 1e-4, 3: 1e-2}[precision], precision=precision,
+           tol_res=0.3 if precision == 3 else None)
+
+
 @pytest.mark.parametrize("N,P", [(1, 1), (2, 0), (3, 12), (5, 2), (6, 1)])
 def test_degrees_and_habc_orders(N, P):
     """Every compiled degree and HABC orders 0 (face rule only), 1, 2, 12
