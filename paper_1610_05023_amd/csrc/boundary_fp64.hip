@@ -102,20 +102,35 @@ __global__ void __launch_bounds__(512, 4) k_boundary(Lvl2 L2, Lvl1 L1, int np3, 
   double* srp = sw + PP * Np;          // 2P x Np
   double* sb = srp + n2 * Np;          // 2P x Np
   double* sS = sb + n2 * Np;           // 2P x Np
-  for (int x = tid; x < Np * Np + 2 * Np; x += nth) cDr[x] = L1.ops[x];
-  for (int x = tid; x < n2 * n2; x += nth) {
-    cG[x] = L1.G[x];
-    cH[x] = L1.H[x];
+  // The constant tables and this line's old state go to LDS, each thread's
+  // entries loaded into registers first (at most one of Dr|LIFT, two of G
+  // and of H, one of Cji, Cij and gamma, four of the state: the launcher
+  // checks the sizes), so that they are in flight with the loads below and
+  // the line costs two rounds of loads, not three.
+  const int nops = Np * Np + 2 * Np, ng = n2 * n2, nq = PP * 2 * Np;
+  double vo = 0.0, vG[2] = {0.0, 0.0}, vH[2] = {0.0, 0.0}, vCji = 0.0, vCij = 0.0, vg = 0.0;
+  double vq[4];
+  if (tid < nops) vo = L1.ops[tid];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int x = tid + h * nth;
+    if (x < ng) {
+      vG[h] = L1.G[x];
+      vH[h] = L1.H[x];
+    }
   }
-  for (int x = tid; x < PP; x += nth) {
-    cCji[x] = L1.Cji[x];
-    cCij[x] = L1.Cij[x];
+  if (tid < PP) {
+    vCji = L1.Cji[tid];
+    vCij = L1.Cij[tid];
   }
-  for (int x = tid; x < P; x += nth) cg[x] = L1.gamma[x];
+  if (tid < P) vg = L1.gamma[tid];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int x = tid + h * nth;
+    vq[h] = x < nq ? b.q1o[(size_t)blk * nq + x] : 0.0;
+  }
   {
     const int l = blk;
-    __syncthreads();
-    for (int x = tid; x < PP * 2 * Np; x += nth) sq[x] = b.q1o[(size_t)l * PP * 2 * Np + x];
     const double rx = L1.geo[l * 4 + 0], irho = L1.geo[l * 4 + 1], Kb = L1.geo[l * 4 + 2],
                  Z = L1.geo[l * 4 + 3];
     int info[8];
@@ -171,6 +186,25 @@ __global__ void __launch_bounds__(512, 4) k_boundary(Lvl2 L2, Lvl1 L1, int np3, 
           }
         }
       }
+    }
+    if (tid < nops) cDr[tid] = vo;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int x = tid + h * nth;
+      if (x < ng) {
+        cG[x] = vG[h];
+        cH[x] = vH[h];
+      }
+    }
+    if (tid < PP) {
+      cCji[tid] = vCji;
+      cCij[tid] = vCij;
+    }
+    if (tid < P) cg[tid] = vg;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int x = tid + h * nth;
+      if (x < nq) sq[x] = vq[h];
     }
     __syncthreads();
 #pragma unroll
@@ -310,8 +344,11 @@ hipError_t launch_boundary(const Lvl2& L2, const Lvl1& L1, const Lvl0& L0,
                     2 * PP * Np1 + 3 * n2 * Np1;
   Bufs b{q2o, q2n, res2, qb2, qb3, q03, q3n, q1o, q1n, res1, qb1, q02};
   // edge nodes at most two per thread; the 2P x Np1 table of outgoing 2D
-  // characteristics one entry per thread
-  if (PP * Np1 > 1024 || n2 * Np1 > 512) return hipErrorInvalidValue;
+  // characteristics one entry per thread; the tables and the line state at
+  // most as many entries per thread as k_boundary loads
+  if (PP * Np1 > 1024 || n2 * Np1 > 512 || Np1 * Np1 + 2 * Np1 > 512 || n2 * n2 > 1024 ||
+      PP > 512 || 2 * PP * Np1 > 2048)
+    return hipErrorInvalidValue;
   const size_t lds = sizeof(double) * a1;
   // one edge node per thread unless P^2 Np1 exceeds the block (P > 10)
   if (PP * Np1 <= 512) {
