@@ -366,45 +366,43 @@ def _host_cpu():
     return os.cpu_count(), model
 
 
-def cpu_baseline():
-    """The FP64 oracle (numpy, as is) on a bounded sample of the workload:
-    the same medium recipe, degree and HABC order on a 20^3 x 6 = 48,000-tet
-    mesh, stepped for 5 steps (25 RK stages), once with numpy's BLAS limited
-    to one thread (the reported value: the oracle is mostly single-threaded
-    elementwise numpy, so this is what one core does) and once with the BLAS
-    pool as numpy starts it.  Per-element work is the same as on the 40^3
-    mesh, so DOF-updates/s per stage carries over."""
-    import numpy as np
+def cpu_baseline(wl):
+    """The FP64 oracle (numpy, as is) on a bounded sample of the bench's own
+    workload `wl` (the same 40^3 x 6 mesh, medium, degree, HABC order and
+    source): its set-up is not timed; then 2 steps (10 Runge-Kutta stages)
+    with numpy's BLAS limited to one thread (the reported value: the oracle is
+    mostly single-threaded elementwise numpy, so this is what one core does)
+    and 1 step with the BLAS pool as numpy starts it.  DOF-updates/s per
+    stage, as the GPU value."""
     import workloads as w
     from oracle.solver import Oracle
     from threadpoolctl import threadpool_info, threadpool_limits
     blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    n, N, P, steps = 20, 4, 6, 5
-    VX, E = w.kuhn_mesh(n)
-    rho, c, *_ = w.layered_medium(n, seed=2)
-    o = Oracle(VX, E, N, P, rho, c)
-    h = 1.0 / n
-    xs = (0.5 + 0.3 * h, 0.5 + 0.2 * h, 0.5 + 0.1 * h)
-    f0 = float(w.source_material(n, xs, c)) / (10.0 * h)
-    o.set_source(xs, f0, 1.25 / f0)
-    dt = w.kuhn_dt(n, N, float(c.max()))
+    N, P, dt = wl["N"], wl["P"], wl["dt"]
+    t_set = time.perf_counter()
+    o = Oracle(wl["VX"], wl["E"], N, P, wl["rho"], wl["c"])
+    o.set_source(wl["xs"], wl["f0"], wl["t0"])
+    t_set = time.perf_counter() - t_set
     U = w.n_unknowns(o.m.K, o.m.Ktri, o.m.Klin, N, P)
     rates = {}
-    for label, limit in (("one", 1), ("all", None)):
+    for label, limit, steps in (("one", 1, 2), ("all", None, 1)):
         o.reset()
         o.s["q3"] = w.random_array(o.s["q3"].shape, 1) * 1e-3
         with threadpool_limits(limits=limit):
             t = time.perf_counter()
             o.step(steps, dt)
-            rates[label] = (U * 5 * steps / (time.perf_counter() - t),
-                            time.perf_counter() - t)
+            el = time.perf_counter() - t
+        rates[label] = (U * 5 * steps / el, el, 5 * steps)
     cpus, model = _host_cpu()
+    n = wl["n"]
     return {"value": rates["one"][0], "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"numpy FP64 oracle, {o.m.K}-tet (20^3 x 6) mesh, N={N}, P={P}, same "
-                      f"layered medium and source recipe, {steps} steps ({5 * steps} RK stages) "
-                      f"in {rates['one'][1]:.1f} s with BLAS on one thread",
+            "sample": f"numpy FP64 oracle on the bench workload itself ({o.m.K}-tet "
+                      f"{n}^3 x 6 mesh, N={N}, P={P}, layered medium, source), "
+                      f"{rates['one'][2]} RK stages in {rates['one'][1]:.1f} s with BLAS on one "
+                      f"thread (oracle set-up, {t_set:.0f} s, not timed)",
             "all_threads_value": rates["all"][0], "all_threads_blas": int(blas),
-            "all_threads_seconds": rates["all"][1], "host_cpus": cpus, "host_cpu_model": model}
+            "all_threads_seconds": rates["all"][1], "all_threads_stages": rates["all"][2],
+            "host_cpus": cpus, "host_cpu_model": model}
 
 
 def main():
@@ -580,7 +578,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and not batch:
         try:
-            cpu = cpu_baseline()
+            cpu = cpu_baseline(wl)
         except Exception as ex:  # reported, never fatal for the GPU figure
             cpu = {"value": None, "error": repr(ex)}
     ptag = {0: "FP64", 2: "FP32-3D", 3: "BF16-contraction FP32-3D"}[prec]
