@@ -401,10 +401,13 @@ def test_one_and_two_cell_meshes(n, N, P, precision):
            tol_res=0.3 if precision == 3 else None)
 
 
-@pytest.mark.parametrize("N,P", [(1, 1), (2, 0), (3, 12), (5, 2), (6, 1)])
+@pytest.mark.parametrize("N,P", [(1, 1), (2, 0), (3, 12), (5, 2), (6, 1), (4, 9), (6, 12)])
 def test_degrees_and_habc_orders(N, P):
-    """Every compiled degree and HABC orders 0 (face rule only), 1, 2, 12
-    (two edge nodes per thread) on all-HABC faces, every array random."""
+    """Every compiled degree and HABC orders 0 (face rule only), 1, 2, 9 (one
+    triangle per face-kernel wave, 7 of its 16 columns idle) and 12 (two
+    edge nodes per thread); N = 6 with P = 12 is the largest case the
+    interface accepts (the line kernel's tables and state at four entries
+    per thread).  All-HABC faces, every array random."""
     case = make_case(n=3, N=N, P=P, init="random", seed=90 + 7 * N + P)
     _check(case, 4, 1e-3)
 
