@@ -89,14 +89,6 @@ def kernel_name(prec, N, tuned):
     return base + "_dma" if on_chip and cand < 6 else base
 
 
-def default_tuning(prec, N):
-    """The untuned 3D launch: the tile-on-chip kernel where the tile fits,
-    XCD-contiguous tile ranges for FP64 at N <= 4, round robin otherwise."""
-    on_chip = N <= (4 if prec == 0 else 5)
-    order = "XCD ranges" if prec == 0 and N <= 4 else "round robin"
-    return f"default ({'tile on chip' if on_chip else 'register streaming'}, {order})"
-
-
 def achieved_gbs(alg_bytes, avg_ms):
     return alg_bytes / (avg_ms * 1e-3) / 1e9
 
@@ -619,7 +611,7 @@ def main():
                    "parallelism": "single GPU",
                    "step_mode": "hip graph per step" if args.graph else "eager launches",
                    "boundary": "learned closure (P = 0)" if args.closure else f"HABC P={wl['P']}",
-                   "tuning": tuned if tuned is not None else default_tuning(prec, wl["N"])},
+                   "tuning": tuned if tuned is not None else "default (tile on chip, XCD ranges)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,

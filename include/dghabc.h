@@ -194,8 +194,7 @@ dgh_status dgh_set_graph(dgh_ctx* ctx, int enable);
  * number of waves (the default is 8 for FP64 at N = 5 and for the FP32
  * and BF16 variants at N = 6, else 4).  Order 0
  * gives each of the 8 XCDs a contiguous range of tiles, order 1 deals tiles
- * round-robin over all workgroups (untuned: order 0 for FP64 with N <= 4,
- * else 1); grid 0, 1, 2 launches 8, 6 or 4 eighths
+ * round-robin over all workgroups; grid 0, 1, 2 launches 8, 6 or 4 eighths
  * of the workgroups that fit on the device at once, each walking more
  * tiles when there are fewer.  Every candidate computes the same step.
  * dgh_set_tuning forces a candidate; dgh_autotune times `launches`

@@ -79,7 +79,6 @@ struct dgh_ctx {
   size_t ev_used = 0;
   // host copies of device-layout constants (kept for tests and re-uploads)
   dgh::Lvl3 L3{};
-  bool tuned = false;                 // a tuning candidate chose the 3D launch
   dgh::Lvl2 L2{};
   dgh::Lvl1 L1{};
   dgh::Lvl0 L0{};
@@ -534,12 +533,6 @@ int default_waves(const dgh_ctx* c) {
   return (c->precision == DGH_FP64 ? c->N == 5 : c->N == 6) ? 8 : 4;
 }
 
-// default item order of the 3D launch: round robin over all workgroups,
-// measured ahead in the step for the FP32 and BF16 variants and for FP64 at
-// N >= 5 (0.6-1.9% per launch); XCD-contiguous ranges for the FP64
-// tile-on-chip kernel (N <= 4), measured ahead there (0.3%)
-int default_order(const dgh_ctx* c) { return (c->precision == DGH_FP64 && c->N <= 4) ? 0 : 1; }
-
 void fill_levels(dgh_ctx* c) {
   const dgh::Mesh& m = c->mesh;
   const Layout& L = c->lay;
@@ -548,7 +541,6 @@ void fill_levels(dgh_ctx* c) {
   a.ntile = c->ntile;
   if (a.eighths == 0) a.eighths = 8;   // the whole resident grid unless tuned
   if (a.waves == 0) a.waves = default_waves(c);
-  if (!c->tuned) a.order = default_order(c);
   a.N = m.N;
   a.Np = m.tet.Np;
   a.Nfp = m.tet.Nfp;
@@ -1157,7 +1149,6 @@ void apply_tuning(dgh_ctx* c, int candidate) {
   }
   c->L3.order = (candidate / 3) & 1;
   c->L3.eighths = kGrids[candidate % 3];
-  c->tuned = true;
 }
 }  // namespace
 
@@ -1194,7 +1185,6 @@ dgh_status dgh_autotune(dgh_ctx* c, int launches, int* best, double* ms) {
   HIPCHECK(c, hipEventCreate(&e1));
   const int keep_kvar = c->L3.kvar, keep_order = c->L3.order, keep_eighths = c->L3.eighths,
             keep_waves = c->L3.waves;
-  const bool keep_tuned = c->tuned;
   double tbest = 0.0;
   int ibest = -1;
   hipError_t err = hipSuccess;
@@ -1226,7 +1216,6 @@ dgh_status dgh_autotune(dgh_ctx* c, int launches, int* best, double* ms) {
     c->L3.order = keep_order;
     c->L3.eighths = keep_eighths;
     c->L3.waves = keep_waves;
-    c->tuned = keep_tuned;
     return hipfail(c, err, "autotune");
   }
   apply_tuning(c, ibest);
